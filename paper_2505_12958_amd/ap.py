@@ -1,0 +1,340 @@
+"""Python binding of the AP C ABI (include/ap.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of ``libap.so``; this module
+only converts torch device tensors and numpy model arrays into the C
+structs and calls the library on the current HIP stream.  There is no CPU
+fallback: if the library or a GPU is missing, loading fails loudly.
+
+Layout: positions, velocities and forces are (3, N) float64 device tensors
+(structure of arrays); lambda and per-atom energies are (N,) float64; the
+virial is (n_systems, 9) float64 with entry 3a+b = -sum d_a G_b.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libap.so")
+
+AP_OK, AP_ERR_ARG, AP_ERR_NBR_CAPACITY, AP_ERR_BOX, AP_ERR_NONFINITE, AP_ERR_HIP, AP_ERR_NOMEM, \
+    AP_ERR_UNSUPPORTED = range(8)
+AP_PREC_FP64, AP_PREC_MIXED = 0, 1
+AP_OVERWRITE, AP_ACCUMULATE = 0, 1
+STATUS = {0: "AP_OK", 1: "AP_ERR_ARG", 2: "AP_ERR_NBR_CAPACITY", 3: "AP_ERR_BOX",
+          4: "AP_ERR_NONFINITE", 5: "AP_ERR_HIP", 6: "AP_ERR_NOMEM", 7: "AP_ERR_UNSUPPORTED"}
+
+
+class APError(RuntimeError):
+    def __init__(self, status, msg, needed=None):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.needed = needed
+
+
+class Systems(C.Structure):
+    _fields_ = [("n_systems", C.c_int32), ("n_atoms", C.c_int64), ("sys_offset", C.POINTER(C.c_int64)),
+                ("box", C.POINTER(C.c_double)), ("periodic", C.c_uint8 * 3), ("cutoff", C.c_double)]
+
+
+class NList(C.Structure):
+    _fields_ = [("nbr", C.c_void_p), ("count", C.c_void_p), ("rev", C.c_void_p), ("capacity", C.c_int32)]
+
+
+class Table(C.Structure):
+    _fields_ = [("x0", C.c_double), ("dx", C.c_double), ("n_knots", C.c_int32),
+                ("coef", C.POINTER(C.c_double))]
+
+
+class EamTables(C.Structure):
+    _fields_ = [("phi", Table), ("rho", Table), ("F", Table)]
+
+
+class AceModel(C.Structure):
+    _fields_ = [("n_max", C.c_int32), ("l_max", C.c_int32), ("nu_max", C.c_int32), ("K", C.c_int32),
+                ("r_c", C.c_double), ("W", C.POINTER(C.c_double)), ("n_funcs", C.c_int32),
+                ("funcs", C.POINTER(C.c_int32)), ("c1", C.POINTER(C.c_double)),
+                ("c2", C.POINTER(C.c_double))]
+
+
+class LambdaRule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double), ("centre", C.c_double * 3),
+                ("r_full", C.c_double), ("taper", C.c_double), ("z_surface_min", C.c_double),
+                ("mask", C.c_void_p)]
+
+
+class MDState(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("force", C.c_void_p),
+                ("e_atom", C.c_void_p), ("lambda_", C.c_void_p), ("mass", C.c_void_p),
+                ("fixed", C.c_void_p), ("ace_list", C.c_void_p), ("n_ace", C.c_void_p),
+                ("nl", NList), ("rule", LambdaRule), ("dt", C.c_double),
+                ("ind_centre", C.c_double * 3), ("ind_vel", C.c_double * 3),
+                ("ind_dir", C.c_double * 3), ("ind_R", C.c_double), ("ind_K", C.c_double),
+                ("virial", C.c_void_p), ("e_sys", C.c_void_p), ("e_ind", C.c_void_p),
+                ("load", C.c_void_p), ("check_every", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libap.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.ap_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(EamTables), C.POINTER(AceModel)]
+        L.ap_destroy.argtypes = [vp]
+        L.ap_last_error.argtypes = [vp]
+        L.ap_last_error.restype = C.c_char_p
+        L.ap_version.restype = C.c_char_p
+        L.ap_build_neighbors.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList),
+                                         C.POINTER(i32), vp]
+        L.ap_blend.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(LambdaRule), vp, vp, vp, vp]
+        L.ap_eam_forces.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList), vp, vp, vp, vp,
+                                    C.c_uint32, vp]
+        L.ap_ace_forces.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList), vp, vp, vp, vp, vp,
+                                    vp, C.c_uint32, vp]
+        L.ap_indenter.argtypes = [vp, C.POINTER(Systems), vp, vp, C.POINTER(d), d, d, C.POINTER(d),
+                                  vp, vp, vp, vp]
+        L.ap_reduce_energy.argtypes = [vp, C.POINTER(Systems), vp, vp, vp]
+        L.ap_step.argtypes = [vp, C.POINTER(Systems), C.POINTER(MDState), i32, vp]
+        L.ap_check.argtypes = [vp, vp]
+        for f in ("ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_eam_forces",
+                  "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
+           "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
+           "ap_check", "ap_version")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class SystemsArg:
+    """Host-side ap_systems with the arrays it points to kept alive."""
+
+    def __init__(self, box, sys_offset, periodic, cutoff):
+        self.box = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(-1, 9))
+        self.off = np.ascontiguousarray(np.asarray(sys_offset, dtype=np.int64))
+        self.c = Systems()
+        self.c.n_systems = len(self.box)
+        self.c.n_atoms = int(self.off[-1])
+        self.c.sys_offset = self.off.ctypes.data_as(C.POINTER(C.c_int64))
+        self.c.box = _dptr(self.box)
+        for k in range(3):
+            self.c.periodic[k] = 1 if periodic[k] else 0
+        self.c.cutoff = float(cutoff)
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.box, wl.sys_offset, wl.periodic, wl.cutoff)
+
+    @property
+    def n_atoms(self):
+        return int(self.off[-1])
+
+    @property
+    def n_systems(self):
+        return len(self.box)
+
+
+def rule_struct(rule, mask_dev=None):
+    r = LambdaRule()
+    r.kind = int(rule.kind)
+    r.value = float(rule.value)
+    for k in range(3):
+        r.centre[k] = float(rule.centre[k])
+    r.r_full = float(rule.r_full)
+    r.taper = float(rule.taper) if rule.taper else 1.0
+    r.z_surface_min = float(rule.z_surface_min)
+    r.mask = None if mask_dev is None else mask_dev.data_ptr()
+    return r
+
+
+class NeighbourList:
+    """Caller-owned device arrays of an ap_nlist."""
+
+    def __init__(self, n_atoms, capacity=64, device="cuda"):
+        self.capacity = int(capacity)
+        self.n_atoms = int(n_atoms)
+        self.nbr = torch.empty(self.capacity * max(1, n_atoms), dtype=torch.int32, device=device)
+        self.rev = torch.empty_like(self.nbr)
+        self.count = torch.empty(max(1, n_atoms), dtype=torch.int32, device=device)
+
+    def struct(self):
+        s = NList()
+        s.nbr = self.nbr.data_ptr()
+        s.count = self.count.data_ptr()
+        s.rev = self.rev.data_ptr()
+        s.capacity = self.capacity
+        return s
+
+    def rows(self):
+        """Host copy: list of neighbour index arrays (ascending)."""
+        cnt = self.count.cpu().numpy()[: self.n_atoms]
+        nb = self.nbr.cpu().numpy().reshape(self.capacity, -1)[:, : self.n_atoms]
+        return [nb[: cnt[i], i].copy() for i in range(self.n_atoms)]
+
+
+class Context:
+    """An ap_ctx with a model (EAM tables and/or ACE model) on one device."""
+
+    def __init__(self, eam=None, ace=None, precision=AP_PREC_FP64, device=0):
+        L = lib()
+        self._keep = []
+        eam_s = None
+        if eam is not None:
+            eam_s = EamTables()
+            for name, t in (("phi", eam.phi), ("rho", eam.rho), ("F", eam.F)):
+                coef = np.ascontiguousarray(t.coef, dtype=np.float64)
+                self._keep.append(coef)
+                tab = getattr(eam_s, name)
+                tab.x0, tab.dx, tab.n_knots = float(t.x0), float(t.dx), int(t.n_knots)
+                tab.coef = _dptr(coef)
+        ace_s = None
+        if ace is not None:
+            W = np.ascontiguousarray(ace.W, dtype=np.float64)
+            funcs = np.ascontiguousarray(ace.funcs, dtype=np.int32)
+            c1 = np.ascontiguousarray(ace.c1, dtype=np.float64)
+            c2 = np.ascontiguousarray(ace.c2, dtype=np.float64)
+            self._keep += [W, funcs, c1, c2]
+            ace_s = AceModel(int(ace.n_max), int(ace.l_max), int(ace.nu_max), int(ace.K), float(ace.r_c),
+                             _dptr(W), len(funcs), funcs.ctypes.data_as(C.POINTER(C.c_int32)),
+                             _dptr(c1), _dptr(c2))
+        h = C.c_void_p()
+        st = L.ap_create(C.byref(h), int(device), int(precision),
+                         C.byref(eam_s) if eam_s is not None else None,
+                         C.byref(ace_s) if ace_s is not None else None)
+        if st != AP_OK:
+            raise APError(st, L.ap_last_error(None).decode())
+        self.h = h
+        self.precision = precision
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, needed=None):
+        if st != AP_OK:
+            raise APError(st, lib().ap_last_error(self.h).decode(), needed)
+
+    # ---- entry points -------------------------------------------------
+    def build_neighbors(self, sysarg, pos, nl, check=True):
+        need = C.c_int32(0)
+        st = lib().ap_build_neighbors(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(nl.struct()),
+                                      C.byref(need) if check else None, _stream())
+        self._check(st, need.value)
+
+    def blend(self, sysarg, pos, rule, lam, ace_list, n_ace, mask=None):
+        r = rule_struct(rule, mask)
+        st = lib().ap_blend(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
+                            _ptr(ace_list), _ptr(n_ace), _stream())
+        self._check(st)
+
+    def eam_forces(self, sysarg, pos, nl, lam, e_atom, force, virial=None, accumulate=False):
+        st = lib().ap_eam_forces(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(nl.struct()), _ptr(lam),
+                                 _ptr(e_atom), _ptr(force), _ptr(virial),
+                                 AP_ACCUMULATE if accumulate else AP_OVERWRITE, _stream())
+        self._check(st)
+
+    def ace_forces(self, sysarg, pos, nl, lam, ace_list, n_ace, e_atom, force, virial=None,
+                   accumulate=False):
+        st = lib().ap_ace_forces(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(nl.struct()), _ptr(lam),
+                                 _ptr(ace_list), _ptr(n_ace), _ptr(e_atom), _ptr(force), _ptr(virial),
+                                 AP_ACCUMULATE if accumulate else AP_OVERWRITE, _stream())
+        self._check(st)
+
+    def indenter(self, sysarg, pos, fixed, centre, R, K, force, e_ind=None, load=None,
+                 direction=(0.0, 0.0, -1.0)):
+        c = (C.c_double * 3)(*[float(x) for x in centre])
+        dvec = (C.c_double * 3)(*[float(x) for x in direction])
+        st = lib().ap_indenter(self.h, C.byref(sysarg.c), _ptr(pos), _ptr(fixed), c, float(R), float(K),
+                               dvec, _ptr(force), _ptr(e_ind), _ptr(load), _stream())
+        self._check(st)
+
+    def reduce_energy(self, sysarg, e_atom, e_sys):
+        st = lib().ap_reduce_energy(self.h, C.byref(sysarg.c), _ptr(e_atom), _ptr(e_sys), _stream())
+        self._check(st)
+
+    def step(self, sysarg, state, n_steps):
+        st = lib().ap_step(self.h, C.byref(sysarg.c), C.byref(state.c), int(n_steps), _stream())
+        self._check(st)
+        state.pull_indenter()
+
+    def check(self):
+        self._check(lib().ap_check(self.h, _stream()))
+
+
+class MD:
+    """Device-resident MD state (ap_md_state) for a workload."""
+
+    def __init__(self, wl, capacity=64, device="cuda"):
+        N = wl.n_atoms
+        f64 = dict(dtype=torch.float64, device=device)
+        self.sys = SystemsArg.from_workload(wl)
+        self.pos = torch.tensor(np.ascontiguousarray(wl.pos.T), **f64)
+        self.vel = torch.tensor(np.ascontiguousarray(wl.vel.T), **f64)
+        self.force = torch.zeros((3, N), **f64)
+        self.e_atom = torch.zeros(N, **f64)
+        self.lam = torch.zeros(N, **f64)
+        self.mass = torch.tensor(wl.masses, **f64)
+        self.fixed = torch.tensor(wl.fixed, dtype=torch.uint8, device=device)
+        self.ace_list = torch.zeros(max(1, N), dtype=torch.int32, device=device)
+        self.n_ace = torch.zeros(1, dtype=torch.int32, device=device)
+        self.nl = NeighbourList(N, capacity, device)
+        self.virial = torch.zeros((wl.n_systems, 9), **f64)
+        self.e_sys = torch.zeros(wl.n_systems, **f64)
+        self.e_ind = torch.zeros(1, **f64)
+        self.load = torch.zeros(1, **f64)
+        self.mask = (torch.tensor(wl.rule.mask, dtype=torch.uint8, device=device)
+                     if wl.rule.mask is not None else None)
+        c = MDState()
+        c.pos, c.vel, c.force = self.pos.data_ptr(), self.vel.data_ptr(), self.force.data_ptr()
+        c.e_atom, c.lambda_, c.mass = self.e_atom.data_ptr(), self.lam.data_ptr(), self.mass.data_ptr()
+        c.fixed = self.fixed.data_ptr()
+        c.ace_list, c.n_ace = self.ace_list.data_ptr(), self.n_ace.data_ptr()
+        c.nl = self.nl.struct()
+        c.rule = rule_struct(wl.rule, self.mask)
+        c.dt = float(wl.dt)
+        ind = wl.indenter or {}
+        K = float(ind.get("K", 0.0))
+        for k in range(3):
+            c.ind_centre[k] = float(ind["centre"][k]) if K > 0 else 0.0
+            c.ind_vel[k] = float(ind["vel"][k]) if K > 0 else 0.0
+            c.ind_dir[k] = (0.0, 0.0, -1.0)[k]
+        c.ind_R = float(ind.get("R", 1.0)) if K > 0 else 1.0
+        c.ind_K = K
+        c.virial, c.e_sys = self.virial.data_ptr(), self.e_sys.data_ptr()
+        c.e_ind, c.load = self.e_ind.data_ptr(), self.load.data_ptr()
+        c.check_every = 0
+        self.c = c
+        self.ind_centre = np.array(c.ind_centre[:])
+
+    def pull_indenter(self):
+        self.ind_centre = np.array(self.c.ind_centre[:])

@@ -1,0 +1,846 @@
+// Host side of the AP library: the extern "C" entry points of include/ap.h,
+// argument validation, model folding (coupling coefficients, folded
+// coefficient matrices, adjoint lists), system geometry, scratch management.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "ap_internal.h"
+
+namespace ap {
+
+static thread_local std::string g_create_err;
+
+ap_status fail(Ctx* ctx, ap_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg; else g_create_err = msg;
+  return s;
+}
+
+ap_status fail_hip(Ctx* ctx, hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what,
+           file, line);
+  return fail(ctx, e == hipErrorOutOfMemory ? AP_ERR_NOMEM : AP_ERR_HIP, buf);
+}
+
+ap_status ensure(Ctx* ctx, Buffer& b, size_t bytes) {
+  if (bytes <= b.bytes && b.p) return AP_OK;
+  if (b.p) {
+    AP_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail_hip(ctx, e, "hipMalloc(scratch)", __FILE__, __LINE__);
+  }
+  b.bytes = want;
+  return AP_OK;
+}
+
+static void release(Buffer& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <typename T>
+static ap_status upload(Ctx* ctx, Buffer& b, const std::vector<T>& v) {
+  ap_status st = ensure(ctx, b, std::max<size_t>(1, v.size()) * sizeof(T));
+  if (st != AP_OK) return st;
+  if (!v.empty()) AP_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return AP_OK;
+}
+
+template <typename T>
+static ap_status upload_owned(Ctx* ctx, const std::vector<T>& v, const T** out) {
+  ctx->owned.emplace_back();
+  ap_status st = upload(ctx, ctx->owned.back(), v);
+  *out = (const T*)ctx->owned.back().p;
+  return st;
+}
+
+// --------------------------------------------------------------------------
+// box geometry (scalar FP64, no contraction: the inverse must equal the
+// cofactor formula bit for bit)
+static void box_inverse(const double* H, double* Hi) {
+#pragma clang fp contract(off)
+  const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7],
+               i = H[8];
+  const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  Hi[0] = (e * i - f * h) / det;
+  Hi[1] = (c * h - b * i) / det;
+  Hi[2] = (b * f - c * e) / det;
+  Hi[3] = (f * g - d * i) / det;
+  Hi[4] = (a * i - c * g) / det;
+  Hi[5] = (c * d - a * f) / det;
+  Hi[6] = (d * h - e * g) / det;
+  Hi[7] = (b * g - a * h) / det;
+  Hi[8] = (a * e - b * d) / det;
+}
+
+static ap_status prepare_systems(Ctx* ctx, const ap_systems* sys, SysView* sv) {
+  if (!sys) return fail(ctx, AP_ERR_ARG, "sys is NULL");
+  if (sys->n_systems < 1 || sys->n_systems > kMaxSys) return fail(ctx, AP_ERR_ARG, "n_systems out of range");
+  if (sys->n_atoms < 0 || sys->n_atoms > (int64_t)INT32_MAX / 2)
+    return fail(ctx, AP_ERR_ARG, "n_atoms out of range");
+  if (!sys->sys_offset || !sys->box) return fail(ctx, AP_ERR_ARG, "sys_offset/box is NULL");
+  if (!(sys->cutoff > 0.0) || !std::isfinite(sys->cutoff)) return fail(ctx, AP_ERR_ARG, "cutoff must be > 0");
+  const int ns = sys->n_systems;
+  SysCache& C = ctx->sys;
+  bool same = C.valid && (int)C.off.size() == ns + 1 && C.cutoff == sys->cutoff &&
+              !memcmp(C.periodic, sys->periodic, 3) &&
+              !memcmp(C.off.data(), sys->sys_offset, sizeof(int64_t) * (ns + 1)) &&
+              !memcmp(C.box.data(), sys->box, sizeof(double) * 9 * ns);
+  if (!same) {
+    C.valid = false;
+    if (sys->sys_offset[0] != 0 || sys->sys_offset[ns] != sys->n_atoms)
+      return fail(ctx, AP_ERR_ARG, "sys_offset must run from 0 to n_atoms");
+    for (int s = 0; s < ns; ++s)
+      if (sys->sys_offset[s + 1] < sys->sys_offset[s]) return fail(ctx, AP_ERR_ARG, "sys_offset not monotone");
+    const double rc = sys->cutoff;
+    std::vector<double> Hi(9 * ns, 0.0);
+    std::vector<uint8_t> ortho(ns);
+    std::vector<int32_t> grid(3 * ns), base(ns + 1, 0);
+    int64_t cells = 0;
+    for (int s = 0; s < ns; ++s) {
+      const double* H = sys->box + 9 * s;
+      for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(H[k])) return fail(ctx, AP_ERR_BOX, "box has non-finite entries");
+      const bool o = H[1] == 0 && H[2] == 0 && H[3] == 0 && H[5] == 0 && H[6] == 0 && H[7] == 0;
+      ortho[s] = o;
+      double width[3];
+      if (o) {
+        for (int k = 0; k < 3; ++k) {
+          width[k] = H[4 * k];
+          if (!(width[k] > 0)) return fail(ctx, AP_ERR_BOX, "box diagonal must be positive");
+        }
+      } else {
+        if (!(sys->periodic[0] && sys->periodic[1] && sys->periodic[2]))
+          return fail(ctx, AP_ERR_UNSUPPORTED, "triclinic boxes must be periodic in x, y and z");
+        const double* a = H;
+        const double* b = H + 3;
+        const double* c = H + 6;
+        auto cross = [](const double* u, const double* v, double* w) {
+          w[0] = u[1] * v[2] - u[2] * v[1];
+          w[1] = u[2] * v[0] - u[0] * v[2];
+          w[2] = u[0] * v[1] - u[1] * v[0];
+        };
+        double bc[3], ca[3], ab[3];
+        cross(b, c, bc);
+        cross(c, a, ca);
+        cross(a, b, ab);
+        const double vol = std::fabs(a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2]);
+        if (!(vol > 0)) return fail(ctx, AP_ERR_BOX, "degenerate box");
+        width[0] = vol / std::sqrt(bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+        width[1] = vol / std::sqrt(ca[0] * ca[0] + ca[1] * ca[1] + ca[2] * ca[2]);
+        width[2] = vol / std::sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+        box_inverse(H, &Hi[9 * s]);
+      }
+      for (int k = 0; k < 3; ++k) {
+        if (sys->periodic[k] && width[k] < 2.0 * rc)
+          return fail(ctx, AP_ERR_BOX, "a periodic cell is narrower than twice the cutoff");
+        int g = (int)std::floor(width[k] / (rc * (1.0 + 1e-9)));
+        grid[3 * s + k] = std::max(1, std::min(g, 1024));
+      }
+      cells += (int64_t)grid[3 * s] * grid[3 * s + 1] * grid[3 * s + 2];
+      if (cells > (1 << 28)) return fail(ctx, AP_ERR_BOX, "too many cells");
+      base[s + 1] = (int32_t)cells;
+    }
+    std::vector<int32_t> sys_of(sys->n_atoms);
+    std::vector<int64_t> lo, hi;
+    std::vector<int32_t> sc(ns + 1, 0);
+    for (int s = 0; s < ns; ++s) {
+      for (int64_t i = sys->sys_offset[s]; i < sys->sys_offset[s + 1]; ++i) sys_of[i] = s;
+      for (int64_t a = sys->sys_offset[s]; a < sys->sys_offset[s + 1]; a += kReduceChunk) {
+        lo.push_back(a);
+        hi.push_back(std::min<int64_t>(a + kReduceChunk, sys->sys_offset[s + 1]));
+      }
+      sc[s + 1] = (int32_t)lo.size();
+    }
+    std::vector<int64_t> off(sys->sys_offset, sys->sys_offset + ns + 1);
+    std::vector<double> box(sys->box, sys->box + 9 * ns);
+    ap_status st;
+    if ((st = upload(ctx, C.off_d, off)) || (st = upload(ctx, C.H_d, box)) ||
+        (st = upload(ctx, C.Hi_d, Hi)) || (st = upload(ctx, C.ortho_d, ortho)) ||
+        (st = upload(ctx, C.grid_d, grid)) || (st = upload(ctx, C.cell_base_d, base)) ||
+        (st = upload(ctx, C.sys_of_d, sys_of)) || (st = upload(ctx, C.chunk_lo_d, lo)) ||
+        (st = upload(ctx, C.chunk_hi_d, hi)) || (st = upload(ctx, C.sys_chunk_d, sc)))
+      return st;
+    C.off = off;
+    C.box = box;
+    memcpy(C.periodic, sys->periodic, 3);
+    C.cutoff = sys->cutoff;
+    C.n_cells = (int32_t)cells;
+    C.n_chunks = (int32_t)lo.size();
+    C.valid = true;
+  }
+  sv->n_sys = ns;
+  sv->n_atoms = (int32_t)sys->n_atoms;
+  sv->off = (const int64_t*)C.off_d.p;
+  sv->H = (const double*)C.H_d.p;
+  sv->Hi = (const double*)C.Hi_d.p;
+  sv->ortho = (const uint8_t*)C.ortho_d.p;
+  sv->grid = (const int32_t*)C.grid_d.p;
+  sv->cell_base = (const int32_t*)C.cell_base_d.p;
+  sv->sys_of = (const int32_t*)C.sys_of_d.p;
+  for (int k = 0; k < 3; ++k) sv->per[k] = sys->periodic[k] ? 1 : 0;
+  sv->rc2 = sys->cutoff * sys->cutoff;
+  return AP_OK;
+}
+
+// --------------------------------------------------------------------------
+// Clebsch-Gordan coefficients: Racah's closed form (complex basis), then the
+// change of basis to the real harmonics of ace_basis.h.
+static double fact(int n) {
+  static double f[41] = {0};
+  if (f[0] == 0) {
+    f[0] = 1;
+    for (int k = 1; k <= 40; ++k) f[k] = f[k - 1] * k;
+  }
+  return f[n];
+}
+
+static double cg_complex(int j1, int m1, int j2, int m2, int J, int M) {
+  if (m1 + m2 != M || std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(M) > J) return 0.0;
+  if (J < std::abs(j1 - j2) || J > j1 + j2) return 0.0;
+  const double pre = (2 * J + 1) * fact(J + j1 - j2) * fact(J - j1 + j2) * fact(j1 + j2 - J) /
+                     fact(j1 + j2 + J + 1) * fact(J + M) * fact(J - M) * fact(j1 - m1) *
+                     fact(j1 + m1) * fact(j2 - m2) * fact(j2 + m2);
+  double sum = 0.0;
+  for (int k = 0; k <= j1 + j2 - J; ++k) {
+    const int a[6] = {k, j1 + j2 - J - k, j1 - m1 - k, j2 + m2 - k, J - j2 + m1 + k, J - j1 - m2 + k};
+    bool ok = true;
+    double den = 1.0;
+    for (int t = 0; t < 6; ++t) {
+      if (a[t] < 0) { ok = false; break; }
+      den *= fact(a[t]);
+    }
+    if (ok) sum += ((k & 1) ? -1.0 : 1.0) / den;
+  }
+  return std::sqrt(pre) * sum;
+}
+
+using cplx = std::complex<double>;
+// U[m][mu] (offset by l): real Y_m = sum_mu U[m][mu] Y^mu
+static std::vector<cplx> umat(int l) {
+  const int w = 2 * l + 1;
+  std::vector<cplx> U(w * w, 0.0);
+  const double s = 1.0 / std::sqrt(2.0);
+  for (int m = -l; m <= l; ++m) {
+    const int r = m + l;
+    if (m == 0) {
+      U[r * w + l] = 1.0;
+    } else if (m > 0) {
+      U[r * w + m + l] = ((m & 1) ? -1.0 : 1.0) * s;
+      U[r * w - m + l] = s;
+    } else {
+      const int k = -m;
+      U[r * w + k + l] = cplx(0.0, -((k & 1) ? -1.0 : 1.0) * s);
+      U[r * w - k + l] = cplx(0.0, s);
+    }
+  }
+  return U;
+}
+
+// real coupling tensor C[(m1+l1)][(m2+l2)][(M+L)]
+static bool real_cg(int l1, int l2, int L, std::vector<double>& out) {
+  const int w1 = 2 * l1 + 1, w2 = 2 * l2 + 1, wL = 2 * L + 1;
+  auto U1 = umat(l1), U2 = umat(l2), UL = umat(L);
+  out.assign((size_t)w1 * w2 * wL, 0.0);
+  for (int a = 0; a < w1; ++a)
+    for (int b = 0; b < w2; ++b)
+      for (int c = 0; c < wL; ++c) {
+        cplx acc = 0.0;
+        for (int mu1 = -l1; mu1 <= l1; ++mu1) {
+          const cplx u1 = std::conj(U1[a * w1 + mu1 + l1]);
+          if (u1 == 0.0) continue;
+          for (int mu2 = -l2; mu2 <= l2; ++mu2) {
+            const int mu = mu1 + mu2;
+            if (std::abs(mu) > L) continue;
+            const cplx u2 = std::conj(U2[b * w2 + mu2 + l2]);
+            const cplx uL = UL[c * wL + mu + L];
+            if (u2 == 0.0 || uL == 0.0) continue;
+            acc += uL * u1 * u2 * cg_complex(l1, mu1, l2, mu2, L, mu);
+          }
+        }
+        if (std::fabs(acc.imag()) > 1e-12) return false;
+        out[((size_t)a * w2 + b) * wL + c] = std::fabs(acc.real()) < 1e-15 ? 0.0 : acc.real();
+      }
+  return true;
+}
+
+// --------------------------------------------------------------------------
+static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
+  const int nmax = m->n_max, lmax = m->l_max, K = m->K;
+  if (lmax < 0 || lmax > kMaxL) return fail(ctx, AP_ERR_ARG, "ACE l_max must be in [0, 4]");
+  if (nmax < 1 || nmax > kMaxN) return fail(ctx, AP_ERR_ARG, "ACE n_max must be in [1, 16]");
+  if (K < 1 || K > kMaxK) return fail(ctx, AP_ERR_ARG, "ACE K must be in [1, 16]");
+  if (m->nu_max < 1 || m->nu_max > 4) return fail(ctx, AP_ERR_ARG, "ACE nu_max must be in [1, 4]");
+  if (!(m->r_c > 0)) return fail(ctx, AP_ERR_ARG, "ACE r_c must be > 0");
+  if (m->n_funcs < 0 || (m->n_funcs > 0 && (!m->funcs || !m->c1 || !m->c2)) || !m->W)
+    return fail(ctx, AP_ERR_ARG, "ACE model arrays missing");
+  const int lp1 = lmax + 1, nlm = lp1 * lp1, nA = nmax * nlm;
+  AceDev& a = ctx->ace;
+  a.n_max = nmax;
+  a.l_max = lmax;
+  a.K = K;
+  a.nlm = nlm;
+  a.nA = nA;
+  a.nnl = nmax * lp1;
+  a.rc = m->r_c;
+  // normalisation of the real harmonics (sqrt2 folded in for m > 0)
+  std::vector<double> yn(nlm, 0.0);
+  for (int l = 0; l <= lmax; ++l)
+    for (int mm = 0; mm <= l; ++mm) {
+      double v = std::sqrt((2 * l + 1) / (4.0 * M_PI) * fact(l - mm) / fact(l + mm));
+      yn[l * l + l + mm] = mm ? std::sqrt(2.0) * v : v;
+    }
+  std::vector<double> W(m->W, m->W + (size_t)nmax * lp1 * K);
+  std::vector<float> Wf(W.begin(), W.end());
+  ap_status st;
+  if ((st = upload_owned(ctx, yn, &a.ynorm)) || (st = upload_owned(ctx, W, &a.W)) ||
+      (st = upload_owned(ctx, Wf, &a.Wf)))
+    return st;
+
+  // channels (a <= b, L) used by the function list
+  auto sidx = [&](int n, int l) { return n * lp1 + l; };
+  auto ok_nl = [&](int n, int l) { return n >= 0 && n < nmax && l >= 0 && l <= lmax; };
+  auto coupl = [](int l1, int l2, int L) { return std::abs(l1 - l2) <= L && L <= l1 + l2 && ((l1 + l2 + L) % 2 == 0); };
+  std::map<std::tuple<int, int, int>, int> chan;  // (L, a, b) -> row
+  struct Term { int L, r1, r2; double c1, c2; };
+  std::vector<std::tuple<int, int, int, int, int, int, double, double>> raw;  // kind data
+  auto chan_key = [&](int n1, int l1, int n2, int l2, int L) {
+    int x = sidx(n1, l1), y = sidx(n2, l2);
+    if (x > y) std::swap(x, y);
+    chan[{L, x, y}] = 0;
+    return std::make_tuple(L, x, y);
+  };
+  const int32_t* F = m->funcs;
+  int Lmax = lmax;
+  for (int v = 0; v < m->n_funcs; ++v) {
+    const int32_t* f = F + 10 * v;
+    const int nu = f[0];
+    if (nu < 1 || nu > m->nu_max) return fail(ctx, AP_ERR_ARG, "ACE function has invalid nu");
+    for (int k = 0; k < nu; ++k)
+      if (!ok_nl(f[1 + 2 * k], f[2 + 2 * k])) return fail(ctx, AP_ERR_ARG, "ACE function index out of range");
+    if (nu == 1 && f[2] != 0) return fail(ctx, AP_ERR_ARG, "nu=1 function needs l=0");
+    if (nu == 2 && f[2] != f[4]) return fail(ctx, AP_ERR_ARG, "nu=2 function needs equal l");
+    if (nu == 3 && (f[9] != f[6] || !coupl(f[2], f[4], f[9])))
+      return fail(ctx, AP_ERR_ARG, "nu=3 function: L must equal l3 and couple (l1, l2) with an even sum");
+    if (nu == 4 && (!coupl(f[2], f[4], f[9]) || !coupl(f[6], f[8], f[9])))
+      return fail(ctx, AP_ERR_ARG, "nu=4 function: L must couple (l1,l2) and (l3,l4) with even sums");
+    if (nu == 2) chan_key(f[1], f[2], f[3], f[4], 0);
+    if (nu == 3) chan_key(f[1], f[2], f[3], f[4], f[9]);
+    if (nu == 4) {
+      chan_key(f[1], f[2], f[3], f[4], f[9]);
+      chan_key(f[5], f[6], f[7], f[8], f[9]);
+    }
+    if (nu >= 3) Lmax = std::max(Lmax, (int)f[9]);
+  }
+  a.L_max = Lmax;
+  int nch[2 * kMaxL + 1] = {0};
+  for (auto& kv : chan) kv.second = nch[std::get<0>(kv.first)]++;
+  int max_xsize = 0;
+  for (int L = 0; L <= Lmax; ++L) {
+    a.nch[L] = nch[L];
+    a.has_arow[L] = L <= lmax ? 1 : 0;
+    a.nrow[L] = nch[L] + (L <= lmax ? nmax : 0) + (L == 0 ? 1 : 0);
+    max_xsize = std::max(max_xsize, a.nrow[L] * (2 * L + 1));
+  }
+  a.max_xsize = max_xsize;
+  auto arow = [&](int n, int L) { return nch[L] + n; };
+  auto one_row = [&]() { return nch[0] + nmax; };
+
+  // X-building CSR and adjoint lists per L
+  std::vector<int32_t> xb_ptr, xb_s1, xb_s2;
+  std::vector<double> xb_c;
+  std::vector<int32_t> ad_ptr, ad_z, ad_p;
+  std::vector<double> ad_c;
+  std::map<std::tuple<int, int, int>, std::vector<double>> cgcache;
+  for (int L = 0; L <= Lmax; ++L) {
+    const int w = 2 * L + 1;
+    a.xb_off[L] = (int32_t)xb_ptr.size();
+    std::vector<std::vector<std::tuple<int, int, double>>> rows(nch[L] * w);
+    std::vector<std::vector<std::tuple<int, int, double>>> adj(nA);
+    for (auto& kv : chan) {
+      if (std::get<0>(kv.first) != L) continue;
+      const int x = std::get<1>(kv.first), y = std::get<2>(kv.first);
+      const int n1 = x / lp1, l1 = x % lp1, n2 = y / lp1, l2 = y % lp1;
+      auto key = std::make_tuple(l1, l2, L);
+      if (!cgcache.count(key)) {
+        std::vector<double> c;
+        if (!real_cg(l1, l2, L, c)) return fail(ctx, AP_ERR_ARG, "complex coupling coefficient");
+        cgcache[key] = c;
+      }
+      const auto& C = cgcache[key];
+      const int w1 = 2 * l1 + 1, w2 = 2 * l2 + 1;
+      for (int M = 0; M < w; ++M)
+        for (int p = 0; p < w1; ++p)
+          for (int q = 0; q < w2; ++q) {
+            const double c = C[((size_t)p * w2 + q) * w + M];
+            if (c == 0.0) continue;
+            const int s1 = n1 * nlm + l1 * l1 + p, s2 = n2 * nlm + l2 * l2 + q;
+            const int dst = kv.second * w + M;
+            rows[dst].emplace_back(s1, s2, c);
+            adj[s1].emplace_back(dst, s2, c);
+            adj[s2].emplace_back(dst, s1, c);
+          }
+    }
+    xb_ptr.push_back((int32_t)xb_s1.size());
+    for (auto& r : rows) {
+      for (auto& t : r) {
+        xb_s1.push_back(std::get<0>(t));
+        xb_s2.push_back(std::get<1>(t));
+        xb_c.push_back(std::get<2>(t));
+      }
+      xb_ptr.push_back((int32_t)xb_s1.size());
+    }
+    a.ad_off[L] = (int32_t)ad_ptr.size();
+    ad_ptr.push_back((int32_t)ad_z.size());
+    for (auto& r : adj) {
+      for (auto& t : r) {
+        ad_z.push_back(std::get<0>(t));
+        ad_p.push_back(std::get<1>(t));
+        ad_c.push_back(std::get<2>(t));
+      }
+      ad_ptr.push_back((int32_t)ad_z.size());
+    }
+  }
+  // folded coefficient matrices: phi^(p) = 1/2 sum_L sum_M X_L[:,M]^T C_L^(p) X_L[:,M]
+  std::vector<std::map<std::pair<int, int>, std::pair<double, double>>> Cm(Lmax + 1);
+  auto add = [&](int L, int r, int c, double v1, double v2) {
+    auto& e = Cm[L][{r, c}];
+    e.first += v1;
+    e.second += v2;
+  };
+  auto sym = [&](int L, int r, int c, double v1, double v2) {
+    if (r == c) {
+      add(L, r, r, 2 * v1, 2 * v2);
+    } else {
+      add(L, r, c, v1, v2);
+      add(L, c, r, v1, v2);
+    }
+  };
+  auto ch = [&](int n1, int l1, int n2, int l2, int L) {
+    int x = sidx(n1, l1), y = sidx(n2, l2);
+    if (x > y) std::swap(x, y);
+    return chan[{L, x, y}];
+  };
+  for (int v = 0; v < m->n_funcs; ++v) {
+    const int32_t* f = F + 10 * v;
+    const double c1 = m->c1[v], c2 = m->c2[v];
+    switch (f[0]) {
+      case 1: sym(0, arow(f[1], 0), one_row(), c1, c2); break;
+      case 2: sym(0, ch(f[1], f[2], f[3], f[4], 0), one_row(), c1, c2); break;
+      case 3: sym(f[9], ch(f[1], f[2], f[3], f[4], f[9]), arow(f[5], f[9]), c1, c2); break;
+      case 4: sym(f[9], ch(f[1], f[2], f[3], f[4], f[9]), ch(f[5], f[6], f[7], f[8], f[9]), c1, c2); break;
+    }
+  }
+  std::vector<int32_t> cx_ptr, cx_col;
+  std::vector<double2> cx_val;
+  for (int L = 0; L <= Lmax; ++L) {
+    a.cx_off[L] = (int32_t)cx_ptr.size();
+    std::vector<std::vector<std::pair<int, std::pair<double, double>>>> rows(a.nrow[L]);
+    for (auto& kv : Cm[L]) rows[kv.first.first].push_back({kv.first.second, kv.second});
+    cx_ptr.push_back((int32_t)cx_col.size());
+    for (auto& r : rows) {
+      for (auto& t : r) {
+        cx_col.push_back(t.first);
+        cx_val.push_back(make_double2(t.second.first, t.second.second));
+      }
+      cx_ptr.push_back((int32_t)cx_col.size());
+    }
+  }
+  if ((st = upload_owned(ctx, xb_ptr, &a.xb_ptr)) || (st = upload_owned(ctx, xb_s1, &a.xb_s1)) ||
+      (st = upload_owned(ctx, xb_s2, &a.xb_s2)) || (st = upload_owned(ctx, xb_c, &a.xb_c)) ||
+      (st = upload_owned(ctx, ad_ptr, &a.ad_ptr)) || (st = upload_owned(ctx, ad_z, &a.ad_z)) ||
+      (st = upload_owned(ctx, ad_p, &a.ad_p)) || (st = upload_owned(ctx, ad_c, &a.ad_c)) ||
+      (st = upload_owned(ctx, cx_ptr, &a.cx_ptr)) || (st = upload_owned(ctx, cx_col, &a.cx_col)) ||
+      (st = upload_owned(ctx, cx_val, &a.cx_val)))
+    return st;
+  ctx->ace_lds = ace_lds_bytes(a, ctx->precision);
+  if (ctx->ace_lds > 160 * 1024) return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for LDS");
+  return AP_OK;
+}
+
+static ap_status upload_table(Ctx* ctx, const ap_table& t, TableDev* d, const char* name) {
+  if (t.n_knots < 2 || !(t.dx > 0) || !t.coef)
+    return fail(ctx, AP_ERR_ARG, std::string("invalid EAM table ") + name);
+  std::vector<double> c(t.coef, t.coef + (size_t)(t.n_knots - 1) * 4);
+  std::vector<float> cf(c.begin(), c.end());
+  d->x0 = t.x0;
+  d->dx = t.dx;
+  d->inv_dx = 1.0 / t.dx;
+  d->n = t.n_knots;
+  ap_status st;
+  if ((st = upload_owned(ctx, c, &d->c)) || (st = upload_owned(ctx, cf, &d->cf))) return st;
+  return AP_OK;
+}
+
+static ap_status check_nl(Ctx* ctx, const ap_nlist* nl) {
+  if (!nl || !nl->nbr || !nl->count || !nl->rev) return fail(ctx, AP_ERR_ARG, "neighbour list arrays missing");
+  if (nl->capacity < 1 || nl->capacity > kMaxCap) return fail(ctx, AP_ERR_ARG, "capacity must be in [1, 256]");
+  return AP_OK;
+}
+
+}  // namespace ap
+
+using namespace ap;
+
+// ============================================================================
+extern "C" {
+
+const char* ap_version(void) { return "ap 0.1 gfx950"; }
+
+const char* ap_last_error(const ap_ctx* c) {
+  const Ctx* ctx = (const Ctx*)c;
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+ap_status ap_create(ap_ctx** out, int32_t device, int32_t precision, const ap_eam_tables* eam,
+                    const ap_ace_model* ace) {
+  if (!out) return fail(nullptr, AP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (precision != AP_PREC_FP64 && precision != AP_PREC_MIXED)
+    return fail(nullptr, AP_ERR_ARG, "precision must be AP_PREC_FP64 or AP_PREC_MIXED");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, AP_ERR_HIP, "no such HIP device");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, AP_ERR_HIP, "hipSetDevice failed");
+  Ctx* ctx = new Ctx();
+  ctx->device = device;
+  ctx->precision = precision;
+  ap_status st = AP_OK;
+  if (eam) {
+    if ((st = upload_table(ctx, eam->phi, &ctx->phi, "phi")) ||
+        (st = upload_table(ctx, eam->rho, &ctx->rho, "rho")) ||
+        (st = upload_table(ctx, eam->F, &ctx->F, "F"))) {
+      g_create_err = ctx->err;
+      ap_destroy((ap_ctx*)ctx);
+      return st;
+    }
+    ctx->has_eam = true;
+  }
+  if (ace) {
+    if ((st = fold_ace(ctx, ace)) != AP_OK) {
+      g_create_err = ctx->err;
+      ap_destroy((ap_ctx*)ctx);
+      return st;
+    }
+    ctx->has_ace = true;
+  }
+  if ((st = ensure(ctx, ctx->flags, 64)) != AP_OK) {
+    g_create_err = ctx->err;
+    ap_destroy((ap_ctx*)ctx);
+    return st;
+  }
+  hipMemset(ctx->flags.p, 0, 64);
+  hipDeviceSynchronize();
+  *out = (ap_ctx*)ctx;
+  return AP_OK;
+}
+
+ap_status ap_destroy(ap_ctx* c) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return AP_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& b : ctx->owned) release(b);
+  SysCache& C = ctx->sys;
+  for (Buffer* b : {&C.off_d, &C.H_d, &C.Hi_d, &C.ortho_d, &C.grid_d, &C.cell_base_d, &C.sys_of_d,
+                    &C.chunk_lo_d, &C.chunk_hi_d, &C.sys_chunk_d})
+    release(*b);
+  for (Buffer* b : {&ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
+                    &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
+                    &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
+                    &ctx->ace_rows_list, &ctx->partials, &ctx->flags, &ctx->ind_atom})
+    release(*b);
+  delete ctx;
+  return AP_OK;
+}
+
+static ap_status scratch_reduce(Ctx* ctx, int m) {
+  return ensure(ctx, ctx->partials, sizeof(double) * (size_t)std::max(1, ctx->sys.n_chunks) * m);
+}
+
+ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_nlist* nl,
+                             int32_t* needed_capacity, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if ((st = check_nl(ctx, nl))) return st;
+  if (!pos && sys && sys->n_atoms > 0) return fail(ctx, AP_ERR_ARG, "pos is NULL");
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  const int64_t N = sv.n_atoms;
+  const int nc = ctx->sys.n_cells;
+  if ((st = ensure(ctx, ctx->cell_count, 4 * (size_t)nc)) ||
+      (st = ensure(ctx, ctx->cell_start, 4 * (size_t)nc)) ||
+      (st = ensure(ctx, ctx->cell_cursor, 4 * (size_t)nc)) ||
+      (st = ensure(ctx, ctx->cell_of, 4 * (size_t)N)) ||
+      (st = ensure(ctx, ctx->cell_atoms, 4 * (size_t)N)) ||
+      (st = ensure(ctx, ctx->cell_pos, 32 * (size_t)N)) ||
+      (st = ensure(ctx, ctx->scan_tmp, 4 * ((size_t)std::max<int64_t>(nc, N) / 4096 + 2))))
+    return st;
+  int32_t* flags = (int32_t*)ctx->flags.p;
+  if (needed_capacity) AP_HIP(launch_fill_i32(flags, 0, 1, s));
+  AP_HIP(launch_fill_i32((int32_t*)ctx->cell_count.p, 0, nc, s));
+  AP_HIP(launch_bin(sv, pos, (int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_count.p, s));
+  AP_HIP(launch_scan_exclusive((const int32_t*)ctx->cell_count.p, (int32_t*)ctx->cell_start.p, nc,
+                               (int32_t*)ctx->scan_tmp.p, s));
+  AP_HIP(hipMemcpyAsync(ctx->cell_cursor.p, ctx->cell_start.p, 4 * (size_t)nc,
+                        hipMemcpyDeviceToDevice, s));
+  AP_HIP(launch_scatter(sv, pos, (const int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_cursor.p,
+                        (int32_t*)ctx->cell_atoms.p, (double4*)ctx->cell_pos.p, s));
+  AP_HIP(launch_fill_nbr(sv, pos, (const int32_t*)ctx->cell_of.p, (const int32_t*)ctx->cell_start.p,
+                         (const int32_t*)ctx->cell_count.p, (const double4*)ctx->cell_pos.p, nl->nbr,
+                         nl->count, nl->capacity, flags, s));
+  AP_HIP(launch_rev((int32_t)N, nl->nbr, nl->count, nl->rev, s));
+  if (needed_capacity) {
+    int32_t need = 0;
+    AP_HIP(hipMemcpyAsync(&need, flags, 4, hipMemcpyDeviceToHost, s));
+    AP_HIP(hipStreamSynchronize(s));
+    if (need > nl->capacity) {
+      *needed_capacity = need;
+      AP_HIP(launch_fill_i32(flags, 0, 1, s));
+      return fail(ctx, AP_ERR_NBR_CAPACITY, "neighbour list capacity exceeded");
+    }
+  }
+  return AP_OK;
+}
+
+ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_lambda_rule* rule,
+                   double* lambda, int32_t* ace_list, int32_t* n_ace, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (!rule || !lambda || !ace_list || !n_ace) return fail(ctx, AP_ERR_ARG, "blend arguments missing");
+  if (rule->kind < AP_LAMBDA_CONST || rule->kind > AP_LAMBDA_MASK) return fail(ctx, AP_ERR_ARG, "bad rule kind");
+  if (rule->kind == AP_LAMBDA_CONST && !(rule->value >= 0.0 && rule->value <= 1.0))
+    return fail(ctx, AP_ERR_ARG, "constant lambda must be in [0, 1]");
+  if (rule->kind != AP_LAMBDA_CONST && (!(rule->r_full >= 0) || !(rule->taper > 0)))
+    return fail(ctx, AP_ERR_ARG, "rule needs r_full >= 0 and taper > 0");
+  if (rule->kind == AP_LAMBDA_MASK && !rule->mask) return fail(ctx, AP_ERR_ARG, "mask rule needs a mask");
+  ap_status st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  if (!pos && sv.n_atoms > 0) return fail(ctx, AP_ERR_ARG, "pos is NULL");
+  const int64_t N = sv.n_atoms;
+  if ((st = ensure(ctx, ctx->e_tmp, 8 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->scan_tmp, 4 * ((size_t)N / 4096 + 2))))
+    return st;
+  int32_t* flag = (int32_t*)ctx->e_tmp.p;
+  AP_HIP(launch_blend((int32_t)N, pos, *rule, lambda, flag, s));
+  AP_HIP(launch_compact((int32_t)N, flag, ace_list, n_ace, (int32_t*)ctx->scan_tmp.p, s));
+  return AP_OK;
+}
+
+static ap_status reduce_into(Ctx* ctx, const SysView& sv, const double* vals, int m, double* out,
+                             bool accumulate, hipStream_t s) {
+  ap_status st;
+  if ((st = scratch_reduce(ctx, m))) return st;
+  AP_HIP(launch_reduce(sv, ctx->sys.n_chunks, (const int64_t*)ctx->sys.chunk_lo_d.p,
+                       (const int64_t*)ctx->sys.chunk_hi_d.p, (const int32_t*)ctx->sys.sys_chunk_d.p,
+                       vals, m, sv.n_atoms, (double*)ctx->partials.p, out, accumulate, s));
+  return AP_OK;
+}
+
+ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_nlist* nl,
+                        const double* lambda, double* e_atom, double* force, double* virial,
+                        uint32_t flags, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!ctx->has_eam) return fail(ctx, AP_ERR_ARG, "context has no EAM tables");
+  if (flags > 1u) return fail(ctx, AP_ERR_ARG, "flags must be AP_OVERWRITE or AP_ACCUMULATE");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if ((st = check_nl(ctx, nl))) return st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  const int64_t N = sv.n_atoms;
+  if (N > 0 && (!pos || !e_atom || !force)) return fail(ctx, AP_ERR_ARG, "pos/e_atom/force is NULL");
+  if ((st = ensure(ctx, ctx->wfp, 8 * (size_t)N)) || (st = ensure(ctx, ctx->eF, 8 * (size_t)N)) ||
+      (st = ensure(ctx, ctx->wgt, 8 * (size_t)N)) ||
+      (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
+    return st;
+  const bool acc = flags == AP_ACCUMULATE;
+  double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
+  AP_HIP(launch_eam(*ctx, sv, pos, nl->nbr, nl->count, (int32_t)N, lambda, (double*)ctx->wfp.p,
+                    (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom, force, vir, acc, s));
+  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
+  return AP_OK;
+}
+
+ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_nlist* nl,
+                        const double* lambda, const int32_t* ace_list, const int32_t* n_ace,
+                        double* e_atom, double* force, double* virial, uint32_t flags,
+                        void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!ctx->has_ace) return fail(ctx, AP_ERR_ARG, "context has no ACE model");
+  if (flags > 1u) return fail(ctx, AP_ERR_ARG, "flags must be AP_OVERWRITE or AP_ACCUMULATE");
+  if (ctx->precision != AP_PREC_FP64) return fail(ctx, AP_ERR_UNSUPPORTED, "mixed ACE path not built");
+  if (ace_list && !n_ace) return fail(ctx, AP_ERR_ARG, "n_ace is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if ((st = check_nl(ctx, nl))) return st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  const int64_t N = sv.n_atoms;
+  if (N > 0 && (!pos || !e_atom || !force)) return fail(ctx, AP_ERR_ARG, "pos/e_atom/force is NULL");
+  const size_t gsz = ctx->precision == AP_PREC_FP64 ? 8 : 4;
+  if ((st = ensure(ctx, ctx->ace_row, 4 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->ace_counter, 64)) ||
+      (st = ensure(ctx, ctx->pair_g, gsz * 3 * (size_t)nl->capacity * std::max<int64_t>(N, 1))) ||
+      (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
+    return st;
+  const bool acc = flags == AP_ACCUMULATE;
+  double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
+  if (!acc) AP_HIP(launch_fill_f64(e_atom, 0.0, N, s));
+  if (vir) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
+  AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
+  AP_HIP(launch_ace(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda, ace_list,
+                    n_ace, (int32_t*)ctx->ace_row.p, (int32_t*)ctx->ace_counter.p, ctx->pair_g.p,
+                    e_atom, vir, s));
+  AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, nl->rev, nl->capacity,
+                           (const int32_t*)ctx->ace_row.p, ctx->pair_g.p, force, acc, s));
+  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
+  return AP_OK;
+}
+
+ap_status ap_indenter(ap_ctx* c, const ap_systems* sys, const double* pos, const uint8_t* fixed,
+                      const double* centre, double R, double K, const double* dir, double* force,
+                      double* e_ind, double* load, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!centre || !dir) return fail(ctx, AP_ERR_ARG, "centre/dir is NULL");
+  if (!(R > 0) || !(K >= 0)) return fail(ctx, AP_ERR_ARG, "indenter needs R > 0 and K >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  if (sv.n_sys != 1) return fail(ctx, AP_ERR_UNSUPPORTED, "the indenter acts on a single system");
+  const int64_t N = sv.n_atoms;
+  if (N > 0 && (!pos || !force)) return fail(ctx, AP_ERR_ARG, "pos/force is NULL");
+  const bool want = e_ind || load;
+  if (want && (st = ensure(ctx, ctx->ind_atom, 16 * (size_t)N + 64))) return st;
+  double* e2 = want ? (double*)ctx->ind_atom.p : nullptr;
+  AP_HIP(launch_indenter((int32_t)N, pos, fixed, centre, R, K, dir, force, e2, s));
+  if (want) {
+    double* out = (double*)ctx->ind_atom.p + 2 * N;
+    if ((st = reduce_into(ctx, sv, e2, 2, out, false, s))) return st;
+    if (e_ind) AP_HIP(hipMemcpyAsync(e_ind, out, 8, hipMemcpyDeviceToDevice, s));
+    if (load) AP_HIP(hipMemcpyAsync(load, out + 1, 8, hipMemcpyDeviceToDevice, s));
+  }
+  return AP_OK;
+}
+
+ap_status ap_reduce_energy(ap_ctx* c, const ap_systems* sys, const double* e_atom, double* e_sys,
+                           void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!e_sys || (!e_atom && sys && sys->n_atoms > 0)) return fail(ctx, AP_ERR_ARG, "e_atom/e_sys is NULL");
+  ap_status st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  return reduce_into(ctx, sv, e_atom, 1, e_sys, false, (hipStream_t)stream);
+}
+
+ap_status ap_check(ap_ctx* c, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t f[2] = {0, 0};
+  AP_HIP(hipMemcpyAsync(f, ctx->flags.p, 8, hipMemcpyDeviceToHost, s));
+  AP_HIP(hipStreamSynchronize(s));
+  AP_HIP(hipGetLastError());
+  if (f[0] || f[1]) {
+    AP_HIP(launch_fill_i32((int32_t*)ctx->flags.p, 0, 2, s));
+    AP_HIP(hipStreamSynchronize(s));
+  }
+  if (f[0]) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "neighbour list capacity exceeded (needed %d)", f[0]);
+    return fail(ctx, AP_ERR_NBR_CAPACITY, buf);
+  }
+  if (f[1]) return fail(ctx, AP_ERR_NONFINITE, "non-finite force detected");
+  return AP_OK;
+}
+
+static ap_status force_eval(Ctx* ctx, const ap_systems* sys, ap_md_state* st, hipStream_t s) {
+  ap_status r;
+  const int64_t N = sys->n_atoms;
+  if ((r = ap_blend((ap_ctx*)ctx, sys, st->pos, &st->rule, st->lambda, st->ace_list, st->n_ace, s)))
+    return r;
+  if ((r = ap_build_neighbors((ap_ctx*)ctx, sys, st->pos, &st->nl, nullptr, s))) return r;
+  bool written = false;
+  if (ctx->has_eam) {
+    if ((r = ap_eam_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->e_atom, st->force,
+                           st->virial, AP_OVERWRITE, s)))
+      return r;
+    written = true;
+  }
+  if (ctx->has_ace) {
+    if ((r = ap_ace_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->ace_list, st->n_ace,
+                           st->e_atom, st->force, st->virial, written ? AP_ACCUMULATE : AP_OVERWRITE,
+                           s)))
+      return r;
+    written = true;
+  }
+  if (!written) {
+    AP_HIP(launch_fill_f64(st->force, 0.0, 3 * N, s));
+    AP_HIP(launch_fill_f64(st->e_atom, 0.0, N, s));
+  }
+  if (st->ind_K > 0) {
+    if ((r = ap_indenter((ap_ctx*)ctx, sys, st->pos, st->fixed, st->ind_centre, st->ind_R, st->ind_K,
+                         st->ind_dir, st->force, st->e_ind, st->load, s)))
+      return r;
+  }
+  return AP_OK;
+}
+
+ap_status ap_step(ap_ctx* c, const ap_systems* sys, ap_md_state* st, int32_t n_steps, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!st || n_steps < 0) return fail(ctx, AP_ERR_ARG, "state is NULL or n_steps < 0");
+  if (!st->pos || !st->vel || !st->force || !st->e_atom || !st->lambda || !st->mass ||
+      !st->ace_list || !st->n_ace)
+    return fail(ctx, AP_ERR_ARG, "md state arrays missing");
+  if (n_steps > 0 && !(st->dt > 0)) return fail(ctx, AP_ERR_ARG, "dt must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status r;
+  SysView sv;
+  if ((r = prepare_systems(ctx, sys, &sv))) return r;
+  const int64_t N = sv.n_atoms;
+  if (n_steps == 0) {
+    if ((r = force_eval(ctx, sys, st, s))) return r;
+  }
+  for (int step = 0; step < n_steps; ++step) {
+    AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed, st->dt,
+                             true, s));
+    for (int k = 0; k < 3; ++k) st->ind_centre[k] += st->dt * st->ind_vel[k];
+    if ((r = force_eval(ctx, sys, st, s))) return r;
+    AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed, st->dt,
+                             false, s));
+    if (st->check_every > 0 && (step + 1) % st->check_every == 0) {
+      AP_HIP(launch_check_finite((int32_t)N, st->force, (int32_t*)ctx->flags.p + 1, s));
+      if ((r = ap_check(c, s))) return r;
+    }
+  }
+  if (st->e_sys && (r = ap_reduce_energy(c, sys, st->e_atom, st->e_sys, s))) return r;
+  return AP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Internal declarations of the AP library: context, device-side model
+// tables, kernel launchers.  Not part of the public ABI (include/ap.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ap.h"
+
+namespace ap {
+
+constexpr int kMaxSys = 1 << 20;
+constexpr int kMaxL = 4;                   // l_max limit of the ACE model
+constexpr int kMaxLM = (kMaxL + 1) * (kMaxL + 1);
+constexpr int kMaxN = 16;
+constexpr int kMaxK = 16;
+constexpr int kMaxCap = 256;               // neighbour-list capacity limit
+constexpr int kReduceChunk = 4096;         // atoms per deterministic partial sum
+
+#define AP_HIP(call)                                                    \
+  do {                                                                  \
+    hipError_t e_ = (call);                                             \
+    if (e_ != hipSuccess) return fail_hip(ctx, e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+// --------------------------------------------------------------------------
+// device view of the systems of one call
+struct SysView {
+  int32_t n_sys;
+  int32_t n_atoms;
+  const int64_t* off;      // n_sys+1
+  const double* H;         // 9 per system
+  const double* Hi;        // 9 per system (triclinic inverse; unused for orthorhombic)
+  const uint8_t* ortho;    // per system
+  const int32_t* grid;     // 3 per system: cells along each axis
+  const int32_t* cell_base;// n_sys+1: first global cell of each system
+  const int32_t* sys_of;   // per atom
+  int32_t per[3];
+  double rc2;
+};
+
+// piecewise-cubic table on device (4 coefficients per interval)
+struct TableDev {
+  double x0, dx, inv_dx;
+  int32_t n;                // knots
+  const double* c;          // (n-1)*4
+  const float* cf;          // same, float
+};
+
+// ACE model folded for the device
+struct AceDev {
+  int32_t n_max, l_max, K, nlm, nA, nnl;
+  int32_t L_max;            // largest coupled L
+  double rc;
+  const double* W;          // [n_max][l_max+1][K]
+  const float* Wf;
+  const double* ynorm;      // N_lm for m >= 0 at l*l + l + m (sqrt2 folded in for m > 0)
+  // per L (0..L_max): X_L rows = [channels | A rows (n, l=L) | one-row (L=0)]
+  int32_t nrow[2 * kMaxL + 1];
+  int32_t nch[2 * kMaxL + 1];
+  int32_t has_arow[2 * kMaxL + 1];
+  // CSR building X: entry e of (channel row r, M) at dst = r*(2L+1)+M
+  int32_t xb_off[2 * kMaxL + 2];    // offset of the L block in xb_ptr (size nch*(2L+1)+1 each)
+  const int32_t* xb_ptr;
+  const int32_t* xb_s1;
+  const int32_t* xb_s2;
+  const double* xb_c;
+  // Cext_L CSR over rows (symmetric, both coefficient sets)
+  int32_t cx_off[2 * kMaxL + 2];    // offset of the L block in cx_ptr (nrow+1 each)
+  const int32_t* cx_ptr;
+  const int32_t* cx_col;
+  const double2* cx_val;
+  // adjoint CSR over A targets: terms (z index, partner A index, coef)
+  int32_t ad_off[2 * kMaxL + 2];    // offset of the L block in ad_ptr (nA+1 each)
+  const int32_t* ad_ptr;
+  const int32_t* ad_z;
+  const int32_t* ad_p;
+  const double* ad_c;
+  int32_t max_xsize;        // max_L nrow*(2L+1)
+};
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct SysCache {
+  bool valid = false;
+  std::vector<int64_t> off;
+  std::vector<double> box;
+  uint8_t periodic[3] = {0, 0, 0};
+  double cutoff = 0;
+  int32_t n_cells = 0;
+  int32_t n_chunks = 0;
+  // device
+  Buffer off_d, H_d, Hi_d, ortho_d, grid_d, cell_base_d, sys_of_d;
+  Buffer chunk_lo_d, chunk_hi_d, sys_chunk_d;  // reduction chunks
+};
+
+struct Ctx {
+  int device = 0;
+  int precision = AP_PREC_FP64;
+  std::string err;
+  bool has_eam = false, has_ace = false;
+  TableDev phi{}, rho{}, F{};
+  AceDev ace{};
+  std::vector<Buffer> owned;            // model tables
+  SysCache sys;
+  // scratch, grown on demand
+  Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
+  Buffer scan_tmp;
+  Buffer wfp, eF, wgt, vir_atom, e_tmp;
+  Buffer ace_row, pair_g, ace_counter, ace_rows_list;
+  Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
+  Buffer ind_atom;
+  size_t ace_lds = 0;
+};
+
+// error helpers (ap_api.hip)
+ap_status fail(Ctx* ctx, ap_status s, const std::string& msg);
+ap_status fail_hip(Ctx* ctx, hipError_t e, const char* what, const char* file, int line);
+ap_status ensure(Ctx* ctx, Buffer& b, size_t bytes);
+
+// launchers ---------------------------------------------------------------
+// neighbours (k_nbr.hip)
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t launch_bin(const SysView& sv, const double* pos, int32_t* cell_of, int32_t* cell_count,
+                      hipStream_t s);
+hipError_t launch_scan_exclusive(const int32_t* in, int32_t* out, int32_t n, int32_t* tmp,
+                                 hipStream_t s);
+hipError_t launch_scatter(const SysView& sv, const double* pos, const int32_t* cell_of,
+                          int32_t* cursor, int32_t* cell_atoms, double4* cell_pos, hipStream_t s);
+hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* cell_of,
+                           const int32_t* cell_start, const int32_t* cell_count,
+                           const double4* cell_pos, int32_t* nbr, int32_t* count, int32_t cap,
+                           int32_t* overflow, hipStream_t s);
+hipError_t launch_rev(int32_t n_atoms, const int32_t* nbr, const int32_t* count, int32_t* rev,
+                      hipStream_t s);
+// switching and compaction (k_misc.hip)
+hipError_t launch_blend(int32_t n, const double* pos, const ap_lambda_rule& rule, double* lambda,
+                        int32_t* flag, hipStream_t s);
+hipError_t launch_compact(int32_t n, const int32_t* flag, int32_t* out_list, int32_t* out_n,
+                          int32_t* tmp, hipStream_t s);
+hipError_t launch_seq(int32_t n, int32_t* out, hipStream_t s);
+// reductions
+hipError_t launch_reduce(const SysView& sv, int32_t n_chunks, const int64_t* chunk_lo,
+                         const int64_t* chunk_hi, const int32_t* sys_chunk, const double* vals,
+                         int32_t m, int64_t stride, double* partials, double* out, bool accumulate,
+                         hipStream_t s);
+// indenter / integration / checks
+hipError_t launch_indenter(int32_t n, const double* pos, const uint8_t* fixed, const double* c,
+                           double R, double K, const double* dir, double* force, double* e_atom2,
+                           hipStream_t s);
+hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* vel,
+                             const double* force, const double* mass, const uint8_t* fixed,
+                             double dt, bool drift, hipStream_t s);
+hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s);
+// EAM (k_eam.hip)
+hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                      const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
+                      double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
+                      bool accumulate, hipStream_t s);
+// ACE (k_ace.hip)
+size_t ace_lds_bytes(const AceDev& a, int precision);
+hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                      const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
+                      const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
+                      int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
+                      hipStream_t s);
+hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                             const int32_t* rev, int32_t cap, const int32_t* ace_row,
+                             const void* pair_g, double* force, bool accumulate, hipStream_t s);
+hipError_t launch_ace_rows(int32_t n_atoms, const int32_t* ace_list, const int32_t* n_ace,
+                           int32_t* ace_row, hipStream_t s);
+
+}  // namespace ap

@@ -1,0 +1,299 @@
+// ACE part of the AP force, FP64 path, and the gather that turns per-bond
+// gradients into forces.
+//
+// Per ACE-active atom i (one workgroup, persistent loop over a global atom
+// counter):
+//   A_nlm = sum_j R_nl(r_ij) Y_lm(u_ij)                    (LDS, 64 bonds at a time)
+//   for each coupled rank L:
+//     X_L = [AA_{c,M} over coupled channels c | A_{n,L,M} | 1 (L = 0)]
+//     Z_L^(p) = C_L^(p) X_L   (folded, symmetric coefficient matrix; sparse rows)
+//     phi^(p) += X_L . Z_L^(p) / 2,   dphi^(p)/dA += (dX_L/dA)^T Z_L^(p)
+//   E_i = phi1 + sqrt(|phi2| + 1e-6)                  (embedding, FP64)
+//   omega = lambda_i (dphi1/dA + sgn(phi2)/(2 sqrt(..)) dphi2/dA)
+//   g_ij = sum_nlm omega_nlm d(R_nl Y_lm)/dd_ij        (per bond, stored)
+// The folded matrix C_L collects every product-basis function: nu=4 terms
+// sit in the channel-channel block, nu=3 in the channel-A block, nu=2 and
+// nu=1 against the constant row, so one quadratic form per L gives phi.
+#include "ace_basis.h"
+#include "ap_internal.h"
+#include "geom.h"
+#include "scan.h"
+
+namespace ap {
+
+constexpr int kAceThreads = 256;
+constexpr int kBondChunk = 64;
+
+
+__global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
+    SysView sv, AceDev a, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
+    const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
+    int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
+    double* __restrict__ vir) {
+  extern __shared__ double lds[];
+  const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
+  double* Rs = lds;                              // [64][nnl]
+  double* Ys = Rs + kBondChunk * nnl;            // [64][nlm]
+  double* A = Ys + kBondChunk * nlm;             // [nA]
+  double* om1 = A + nA;                          // [nA]
+  double* om2 = om1 + nA;                        // [nA]
+  double* X = om2 + nA;                          // [xs]
+  double* Z1 = X + xs;                           // [xs]
+  double* Z2 = Z1 + xs;                          // [xs]
+  double* red = Z2 + xs;                         // [16]
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  const int n = sv.n_atoms;
+  const int n_items = ace_list ? *n_ace_p : n_all;
+  const int lp1 = a.l_max + 1;
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int i = ace_list ? ace_list[item] : item;
+    const double lam = lambda ? lambda[i] : 1.0;
+    const int s = sv.sys_of[i];
+    const bool ortho = sv.ortho[s] != 0;
+    const double* H = sv.H + 9 * s;
+    const double* Hi = sv.Hi + 9 * s;
+    const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    const int c = count[i];
+
+    // ---- atomic basis A
+    for (int e = tid; e < nA; e += kAceThreads) { A[e] = 0.0; om1[e] = 0.0; om2[e] = 0.0; }
+    for (int base = 0; base < c; base += kBondChunk) {
+      const int nb = min(kBondChunk, c - base);
+      if (tid < nb) {
+        const int j = nbr[(int64_t)(base + tid) * n + i];
+        double dx, dy, dz;
+        displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double g[kMaxK], dg[kMaxK];
+        cheb_basis<double>(a.K, a.rc, r, g, dg);
+        for (int nl = 0; nl < nnl; ++nl) {
+          double v = 0.0;
+          for (int k = 0; k < a.K; ++k) v += a.W[nl * a.K + k] * g[k];
+          Rs[tid * nnl + nl] = v;
+        }
+        double Y[kMaxLM];
+        const double ir = 1.0 / r;
+        real_ylm<double>(a.l_max, a.ynorm, dx * ir, dy * ir, dz * ir, r, Y, nullptr);
+        for (int q = 0; q < nlm; ++q) Ys[tid * nlm + q] = Y[q];
+      }
+      __syncthreads();
+      for (int e = tid; e < nA; e += kAceThreads) {
+        const int nn = e / nlm, q = e % nlm;
+        int l = 0;
+        while ((l + 1) * (l + 1) <= q) ++l;
+        const int col = nn * lp1 + l;
+        double acc = A[e];
+        for (int t = 0; t < nb; ++t) acc += Rs[t * nnl + col] * Ys[t * nlm + q];
+        A[e] = acc;
+      }
+      __syncthreads();
+    }
+
+    // ---- folded contraction per coupled rank L
+    double p1 = 0.0, p2 = 0.0;
+    for (int L = 0; L <= a.L_max; ++L) {
+      const int w = 2 * L + 1;
+      const int nr = a.nrow[L], nch = a.nch[L];
+      const int* xptr = a.xb_ptr + a.xb_off[L];
+      for (int e = tid; e < nr * w; e += kAceThreads) {
+        const int row = e / w, M = e % w;
+        double v;
+        if (row < nch) {
+          v = 0.0;
+          for (int q = xptr[e]; q < xptr[e + 1]; ++q) v += a.xb_c[q] * A[a.xb_s1[q]] * A[a.xb_s2[q]];
+        } else if (a.has_arow[L] && row < nch + a.n_max) {
+          v = A[(row - nch) * nlm + L * L + M];
+        } else {
+          v = 1.0;  // constant row (L = 0 only)
+        }
+        X[e] = v;
+      }
+      __syncthreads();
+      const int* cptr = a.cx_ptr + a.cx_off[L];
+      for (int e = tid; e < nr * w; e += kAceThreads) {
+        const int row = e / w, M = e % w;
+        double z1 = 0.0, z2 = 0.0;
+        for (int q = cptr[row]; q < cptr[row + 1]; ++q) {
+          const double2 cv = a.cx_val[q];
+          const double x = X[a.cx_col[q] * w + M];
+          z1 += cv.x * x;
+          z2 += cv.y * x;
+        }
+        Z1[e] = z1;
+        Z2[e] = z2;
+        p1 += 0.5 * X[e] * z1;
+        p2 += 0.5 * X[e] * z2;
+      }
+      __syncthreads();
+      const int* aptr = a.ad_ptr + a.ad_off[L];
+      for (int t = tid; t < nA; t += kAceThreads) {
+        double g1 = om1[t], g2 = om2[t];
+        for (int q = aptr[t]; q < aptr[t + 1]; ++q) {
+          const double f = a.ad_c[q] * A[a.ad_p[q]];
+          g1 += f * Z1[a.ad_z[q]];
+          g2 += f * Z2[a.ad_z[q]];
+        }
+        const int q = t % nlm;
+        if (a.has_arow[L] && q >= L * L && q < (L + 1) * (L + 1)) {
+          const int z = (nch + t / nlm) * w + (q - L * L);
+          g1 += Z1[z];
+          g2 += Z2[z];
+        }
+        om1[t] = g1;
+        om2[t] = g2;
+      }
+      __syncthreads();
+    }
+    p1 = block_sum_f64<kAceThreads / 64>(p1, red);
+    p2 = block_sum_f64<kAceThreads / 64>(p2, red + 4);
+    const double root = sqrt(fabs(p2) + 1e-6);
+    const double E = p1 + root;
+    const double sp = (p2 >= 0.0 ? 1.0 : -1.0) / (2.0 * root);
+    for (int t = tid; t < nA; t += kAceThreads) om1[t] = lam * (om1[t] + sp * om2[t]);
+    __syncthreads();
+
+    // ---- per-bond gradients and the atom's virial
+    double w9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int sl = tid; sl < c; sl += kAceThreads) {
+      const int j = nbr[(int64_t)sl * n + i];
+      double dx, dy, dz;
+      displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double ir = 1.0 / r;
+      double g[kMaxK], dg[kMaxK];
+      cheb_basis<double>(a.K, a.rc, r, g, dg);
+      double ca[kMaxLM], cb[kMaxLM];
+      for (int q = 0; q < nlm; ++q) { ca[q] = 0.0; cb[q] = 0.0; }
+      for (int nn = 0; nn < a.n_max; ++nn) {
+        for (int l = 0; l <= a.l_max; ++l) {
+          double R = 0.0, dR = 0.0;
+          const double* Wr = a.W + (nn * lp1 + l) * a.K;
+          for (int k = 0; k < a.K; ++k) { R += Wr[k] * g[k]; dR += Wr[k] * dg[k]; }
+          const double* om = om1 + nn * nlm;
+          for (int q = l * l; q < (l + 1) * (l + 1); ++q) {
+            ca[q] += om[q] * R;
+            cb[q] += om[q] * dR;
+          }
+        }
+      }
+      double rad, gx, gy, gz;
+      ylm_contract<double>(a.l_max, a.ynorm, dx * ir, dy * ir, dz * ir, r, ca, cb, rad, gx, gy, gz);
+      gx += rad * dx * ir;
+      gy += rad * dy * ir;
+      gz += rad * dz * ir;
+      double* o = pair_g + ((int64_t)item * cap + sl) * 3;
+      o[0] = gx; o[1] = gy; o[2] = gz;
+      w9[0] -= dx * gx; w9[1] -= dx * gy; w9[2] -= dx * gz;
+      w9[3] -= dy * gx; w9[4] -= dy * gy; w9[5] -= dy * gz;
+      w9[6] -= dz * gx; w9[7] -= dz * gy; w9[8] -= dz * gz;
+    }
+    for (int k = 0; k < 9; ++k) {
+      const double v = block_sum_f64<kAceThreads / 64>(w9[k], red + 8);
+      if (tid == 0 && vir) vir[(int64_t)k * n + i] = v;
+    }
+    if (tid == 0) e_atom[i] += lam * E;
+    __syncthreads();
+  }
+}
+
+size_t ace_lds_bytes(const AceDev& a, int precision) {
+  (void)precision;
+  return sizeof(double) * ((size_t)kBondChunk * (a.nnl + a.nlm) + 3 * (size_t)a.nA +
+                           3 * (size_t)a.max_xsize + 16);
+}
+
+__global__ void k_ace_rows(int n, const int32_t* __restrict__ ace_list,
+                           const int32_t* __restrict__ n_ace, int32_t* __restrict__ row) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = ace_list ? *n_ace : n;
+  if (t < m) row[ace_list ? ace_list[t] : t] = t;
+}
+
+hipError_t launch_ace_rows(int32_t n_atoms, const int32_t* ace_list, const int32_t* n_ace,
+                           int32_t* ace_row, hipStream_t s) {
+  hipError_t e = launch_fill_i32(ace_row, -1, n_atoms, s);
+  if (e != hipSuccess || n_atoms == 0) return e;
+  hipLaunchKernelGGL(k_ace_rows, dim3((n_atoms + 255) / 256), dim3(256), 0, s, n_atoms, ace_list,
+                     n_ace, ace_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                      const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
+                      const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
+                      int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
+                      hipStream_t s) {
+  (void)ace_row;
+  hipError_t e = launch_fill_i32(counter, 0, 1, s);
+  if (e != hipSuccess) return e;
+  int dev = 0, n_cu = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds = ace_lds_bytes(c.ace, c.precision);
+  const int blocks = n_cu * 2;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute((const void*)k_ace_fp64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, nbr,
+                     count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
+                     vir_atom);
+  return hipGetLastError();
+}
+
+// F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only
+template <typename G>
+__global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+                             const int32_t* __restrict__ rev, int cap, const int32_t* __restrict__ row,
+                             const G* __restrict__ g, double* __restrict__ force, int accumulate) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int c = count[k];
+  const int rk = row[k];
+  double fx = 0, fy = 0, fz = 0;
+  for (int s = 0; s < c; ++s) {
+    if (rk >= 0) {
+      const G* o = g + ((int64_t)rk * cap + s) * 3;
+      fx += (double)o[0]; fy += (double)o[1]; fz += (double)o[2];
+    }
+    const int j = nbr[(int64_t)s * n + k];
+    const int rj = row[j];
+    if (rj >= 0) {
+      const int r = rev[(int64_t)s * n + k];
+      if (r >= 0) {
+        const G* o = g + ((int64_t)rj * cap + r) * 3;
+        fx -= (double)o[0]; fy -= (double)o[1]; fz -= (double)o[2];
+      }
+    }
+  }
+  if (accumulate) {
+    force[k] += fx; force[n + k] += fy; force[2 * n + k] += fz;
+  } else {
+    force[k] = fx; force[n + k] = fy; force[2 * n + k] = fz;
+  }
+}
+
+hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                             const int32_t* rev, int32_t cap, const int32_t* ace_row,
+                             const void* pair_g, double* force, bool accumulate, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  const dim3 g((n_atoms + 255) / 256), b(256);
+  if (c.precision == AP_PREC_FP64)
+    hipLaunchKernelGGL(k_ace_gather<double>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
+                       (const double*)pair_g, force, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_ace_gather<float>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
+                       (const float*)pair_g, force, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace ap

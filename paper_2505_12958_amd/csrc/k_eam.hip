@@ -1,0 +1,151 @@
+// EAM part of the AP force: two gather passes over the full ELL lists, no
+// atomics.  Paper, section "EAM potential": E_i = xi(sum_j zeta(r_ij)) +
+// 1/2 sum_j Phi(r_ij); with weights w_i = 1 - lambda_i the force on atom k is
+// F_k = sum_j [(w_k xi'_k + w_j xi'_j) zeta'(r) + (w_k + w_j) Phi'(r)/2] d_kj/r.
+#include "ap_internal.h"
+#include "geom.h"
+
+namespace ap {
+
+__device__ __forceinline__ void tab_eval(const TableDev& t, double x, bool linear_beyond,
+                                         double& v, double& dv) {
+  int k = (int)floor((x - t.x0) * t.inv_dx);
+  k = k < 0 ? 0 : (k > t.n - 2 ? t.n - 2 : k);
+  const double u = x - (t.x0 + k * t.dx);
+  const double4 c = reinterpret_cast<const double4*>(t.c)[k];
+  v = c.x + u * (c.y + u * (c.z + u * c.w));
+  dv = c.y + u * (2.0 * c.z + u * 3.0 * c.w);
+  const double x_end = t.x0 + (t.n - 1) * t.dx;
+  if (x > x_end) {
+    if (linear_beyond) {
+      const double4 e = reinterpret_cast<const double4*>(t.c)[t.n - 2];
+      const double h = t.dx;
+      const double ve = e.x + h * (e.y + h * (e.z + h * e.w));
+      const double de = e.y + h * (2.0 * e.z + h * 3.0 * e.w);
+      v = ve + de * (x - x_end);
+      dv = de;
+    } else {
+      v = 0.0;
+      dv = 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t, TableDev F_t,
+                                                     const double* __restrict__ pos,
+                                                     const int32_t* __restrict__ nbr,
+                                                     const int32_t* __restrict__ count,
+                                                     const double* __restrict__ lambda,
+                                                     double* __restrict__ wfp,
+                                                     double* __restrict__ eF,
+                                                     double* __restrict__ wgt) {
+  const int n = sv.n_atoms;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double w = lambda ? 1.0 - lambda[i] : 1.0;
+  wgt[i] = w;
+  if (!(w > 0.0)) {
+    wfp[i] = 0.0;
+    eF[i] = 0.0;
+    return;
+  }
+  const int s = sv.sys_of[i];
+  const bool ortho = sv.ortho[s] != 0;
+  const double* H = sv.H + 9 * s;
+  const double* Hi = sv.Hi + 9 * s;
+  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+  const int c = count[i];
+  double rho = 0.0;
+  for (int q = 0; q < c; ++q) {
+    const int j = nbr[(int64_t)q * n + i];
+    double dx, dy, dz;
+    displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double v, dv;
+    tab_eval(rho_t, r, false, v, dv);
+    rho += v;
+  }
+  double Fv, Fp;
+  tab_eval(F_t, rho, true, Fv, Fp);
+  wfp[i] = w * Fp;
+  eF[i] = Fv;
+}
+
+__global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, TableDev phi_t,
+                                                   const double* __restrict__ pos,
+                                                   const int32_t* __restrict__ nbr,
+                                                   const int32_t* __restrict__ count,
+                                                   const double* __restrict__ wfp,
+                                                   const double* __restrict__ eF,
+                                                   const double* __restrict__ wgt,
+                                                   double* __restrict__ e_atom,
+                                                   double* __restrict__ force,
+                                                   double* __restrict__ vir, int accumulate) {
+  const int n = sv.n_atoms;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int s = sv.sys_of[k];
+  const bool ortho = sv.ortho[s] != 0;
+  const double* H = sv.H + 9 * s;
+  const double* Hi = sv.Hi + 9 * s;
+  const double xk = pos[k], yk = pos[n + k], zk = pos[2 * n + k];
+  const double wk = wgt[k], fk = wfp[k];
+  const int c = count[k];
+  double fx = 0, fy = 0, fz = 0, ephi = 0;
+  double v00 = 0, v01 = 0, v02 = 0, v10 = 0, v11 = 0, v12 = 0, v20 = 0, v21 = 0, v22 = 0;
+  for (int q = 0; q < c; ++q) {
+    const int j = nbr[(int64_t)q * n + k];
+    const double wj = wgt[j], fj = wfp[j];
+    if (wk == 0.0 && wj == 0.0) continue;
+    double dx, dy, dz;
+    displacement(ortho, H, Hi, sv.per, xk, yk, zk, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double ir = 1.0 / r;
+    double z, dzr, p, dp;
+    tab_eval(rho_t, r, false, z, dzr);
+    tab_eval(phi_t, r, false, p, dp);
+    const double a = ((fk + fj) * dzr + 0.5 * (wk + wj) * dp) * ir;
+    fx += a * dx;
+    fy += a * dy;
+    fz += a * dz;
+    ephi += p;
+    // virial of atom k's own bond gradient G_kj = (w_k xi'_k zeta' + w_k Phi'/2) d/r
+    const double g = (fk * dzr + 0.5 * wk * dp) * ir;
+    const double gx = g * dx, gy = g * dy, gz = g * dz;
+    v00 -= dx * gx; v01 -= dx * gy; v02 -= dx * gz;
+    v10 -= dy * gx; v11 -= dy * gy; v12 -= dy * gz;
+    v20 -= dz * gx; v21 -= dz * gy; v22 -= dz * gz;
+  }
+  const double e = wk > 0.0 ? wk * (eF[k] + 0.5 * ephi) : 0.0;
+  if (accumulate) {
+    e_atom[k] += e;
+    force[k] += fx;
+    force[n + k] += fy;
+    force[2 * n + k] += fz;
+  } else {
+    e_atom[k] = e;
+    force[k] = fx;
+    force[n + k] = fy;
+    force[2 * n + k] = fz;
+  }
+  if (vir) {
+    vir[0 * (int64_t)n + k] = v00; vir[1 * (int64_t)n + k] = v01; vir[2 * (int64_t)n + k] = v02;
+    vir[3 * (int64_t)n + k] = v10; vir[4 * (int64_t)n + k] = v11; vir[5 * (int64_t)n + k] = v12;
+    vir[6 * (int64_t)n + k] = v20; vir[7 * (int64_t)n + k] = v21; vir[8 * (int64_t)n + k] = v22;
+  }
+}
+
+hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                      const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
+                      double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
+                      bool accumulate, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  const dim3 g((n_atoms + 255) / 256), b(256);
+  hipLaunchKernelGGL(k_eam_density, g, b, 0, s, sv, c.rho, c.F, pos, nbr, count, lambda, wfp, eF,
+                     wgt);
+  hipLaunchKernelGGL(k_eam_force, g, b, 0, s, sv, c.rho, c.phi, pos, nbr, count, wfp, eF, wgt,
+                     e_atom, force, vir_atom, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace ap

@@ -1,0 +1,309 @@
+// Switching parameter, ordered compaction and prefix sums, deterministic
+// per-system reductions, indenter, velocity-Verlet, finiteness check.
+#include "ap_internal.h"
+#include "scan.h"
+
+namespace ap {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// --------------------------------------------------------------------------
+// three-pass multi-block exclusive scan of int32 (tile sums, scan of tile
+// sums in one block, tile-local scan + offset).  mode 0 writes the prefix
+// sums; mode 1 writes, for every i with in[i] != 0, i at out[prefix(i)] and
+// the total at *out_n (ordered compaction of a 0/1 flag array).
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ in, int n,
+                                                            int32_t* __restrict__ sums) {
+  __shared__ int ws[kScanThreads / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = base + k;
+    if (i < n) t += in[i];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+  if (lane == 0) ws[w] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int k = 0; k < kScanThreads / 64; ++k) s += ws[k];
+    sums[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t* __restrict__ sums, int nt,
+                                                    int32_t* __restrict__ total) {
+  // single block, sequential chunks of 1024 with a running carry
+  __shared__ int ws[16];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int b = 0; b < nt; b += 1024) {
+    const int i = b + threadIdx.x;
+    const int v = i < nt ? sums[i] : 0;
+    int incl = wave_incl_scan_i32(v, lane);
+    if (lane == 63) ws[w] = incl;
+    __syncthreads();
+    int off = carry;
+    for (int k = 0; k < w; ++k) off += ws[k];
+    if (i < nt) sums[i] = off + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = off + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in, int n,
+                                                            const int32_t* __restrict__ offs,
+                                                            int32_t* __restrict__ out) {
+  __shared__ int ws[kScanThreads / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = base + k;
+    v[k] = i < n ? in[i] : 0;
+    t += v[k];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int incl = wave_incl_scan_i32(t, lane);
+  if (lane == 63) ws[w] = incl;
+  __syncthreads();
+  int off = offs[blockIdx.x];
+  for (int k = 0; k < w; ++k) off += ws[k];
+  int run = off + incl - t;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int i = base + k;
+    if (i < n) {
+      if (MODE == 0) {
+        out[i] = run;
+      } else if (v[k]) {
+        out[run] = i;
+      }
+    }
+    run += v[k];
+  }
+}
+
+static hipError_t scan_impl(const int32_t* in, int32_t n, int32_t* out, int32_t* total,
+                            int32_t* tmp, int mode, hipStream_t s) {
+  const int nt = (n + kScanTile - 1) / kScanTile;
+  if (nt == 0) {
+    if (total) {
+      hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, 0, total);
+    }
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, nt, total);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_tile_scan<0>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out);
+  else
+    hipLaunchKernelGGL(k_tile_scan<1>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out);
+  return hipGetLastError();
+}
+
+// tmp must hold ceil(n / 4096) + 1 ints
+hipError_t launch_scan_exclusive(const int32_t* in, int32_t* out, int32_t n, int32_t* tmp,
+                                 hipStream_t s) {
+  return scan_impl(in, n, out, nullptr, tmp, 0, s);
+}
+
+hipError_t launch_compact(int32_t n, const int32_t* flag, int32_t* out_list, int32_t* out_n,
+                          int32_t* tmp, hipStream_t s) {
+  return scan_impl(flag, n, out_list, out_n, tmp, 1, s);
+}
+
+__global__ void k_seq(int n, int32_t* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+
+hipError_t launch_seq(int32_t n, int32_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seq, dim3((n + 255) / 256), dim3(256), 0, s, n, out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// switching parameter (ACE weight) from the rule
+__global__ void k_blend(int n, const double* __restrict__ pos, ap_lambda_rule rule,
+                        double* __restrict__ lambda, int32_t* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lam;
+  if (rule.kind == AP_LAMBDA_CONST) {
+    lam = rule.value;
+  } else {
+    const double x = pos[i] - rule.centre[0];
+    const double y = pos[n + i] - rule.centre[1];
+    const double z = pos[2 * n + i] - rule.centre[2];
+    const double d = sqrt(x * x + y * y + z * z);
+    double geo = 0.0;
+    if (d <= rule.r_full) {
+      geo = 1.0;
+    } else if (d < rule.r_full + rule.taper) {
+      geo = 0.5 * (1.0 + cos(M_PI * (d - rule.r_full) / rule.taper));
+    }
+    lam = geo;
+    if (rule.kind == AP_LAMBDA_MASK && rule.mask[i]) lam = 1.0;
+    if (geo == 0.0 && pos[2 * n + i] >= rule.z_surface_min) lam = 0.0;
+  }
+  lambda[i] = lam;
+  flag[i] = lam > 0.0 ? 1 : 0;
+}
+
+hipError_t launch_blend(int32_t n, const double* pos, const ap_lambda_rule& rule, double* lambda,
+                        int32_t* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_blend, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, rule, lambda, flag);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Deterministic per-system sums of m arrays vals[k*stride + i]: one block per
+// chunk of at most kReduceChunk atoms of one system (fixed thread-strided
+// order and fixed tree), then one thread per (system, k) adds the chunk
+// partials of its system in chunk order.
+__global__ __launch_bounds__(256) void k_reduce_chunks(const int64_t* __restrict__ lo,
+                                                       const int64_t* __restrict__ hi,
+                                                       const double* __restrict__ vals, int m,
+                                                       int64_t stride,
+                                                       double* __restrict__ partials) {
+  __shared__ double ws[4];
+  const int c = blockIdx.x;
+  const int64_t a = lo[c], b = hi[c];
+  for (int k = 0; k < m; ++k) {
+    double t = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) t += vals[k * stride + i];
+    t = block_sum_f64<4>(t, ws);
+    if (threadIdx.x == 0) partials[(int64_t)c * m + k] = t;
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_systems(int n_sys, const int32_t* __restrict__ sys_chunk, int m,
+                                 const double* __restrict__ partials, double* __restrict__ out,
+                                 int accumulate) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_sys * m) return;
+  const int s = t / m, k = t % m;
+  double v = 0.0;
+  for (int c = sys_chunk[s]; c < sys_chunk[s + 1]; ++c) v += partials[(int64_t)c * m + k];
+  out[t] = accumulate ? out[t] + v : v;
+}
+
+hipError_t launch_reduce(const SysView& sv, int32_t n_chunks, const int64_t* chunk_lo,
+                         const int64_t* chunk_hi, const int32_t* sys_chunk, const double* vals,
+                         int32_t m, int64_t stride, double* partials, double* out, bool accumulate,
+                         hipStream_t s) {
+  if (n_chunks > 0)
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(n_chunks), dim3(256), 0, s, chunk_lo, chunk_hi, vals,
+                       m, stride, partials);
+  const int nt = sv.n_sys * m;
+  hipLaunchKernelGGL(k_reduce_systems, dim3((nt + 255) / 256), dim3(256), 0, s, sv.n_sys,
+                     sys_chunk, m, partials, out, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// indenter: per-atom energy and load into e2[i], e2[n + i] (reduced later)
+__global__ void k_indenter(int n, const double* __restrict__ pos, const uint8_t* __restrict__ fixed,
+                           double cx, double cy, double cz, double R, double K, double ux,
+                           double uy, double uz, double* __restrict__ force,
+                           double* __restrict__ e2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double e = 0.0, ld = 0.0;
+  if (!(fixed && fixed[i])) {
+    const double x = pos[i] - cx, y = pos[n + i] - cy, z = pos[2 * n + i] - cz;
+    const double d = sqrt(x * x + y * y + z * z);
+    if (d < R) {
+      const double p = R - d;
+      e = K / 3.0 * p * p * p;
+      const double f = K * p * p / d;
+      force[i] += f * x;
+      force[n + i] += f * y;
+      force[2 * n + i] += f * z;
+      ld = f * x * ux + f * y * uy + f * z * uz;
+    }
+  }
+  if (e2) {
+    e2[i] = e;
+    e2[n + i] = ld;
+  }
+}
+
+hipError_t launch_indenter(int32_t n, const double* pos, const uint8_t* fixed, const double* c,
+                           double R, double K, const double* dir, double* force, double* e2,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_indenter, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, fixed, c[0], c[1],
+                     c[2], R, K, dir[0], dir[1], dir[2], force, e2);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// velocity Verlet: half kick, optional drift with periodic wrap
+constexpr double kAcc = 9.648533212e-3;  // (eV/A/amu) -> A/fs^2
+
+__global__ void k_kick_drift(int n, SysView sv, double* __restrict__ pos, double* __restrict__ vel,
+                             const double* __restrict__ force, const double* __restrict__ mass,
+                             const uint8_t* __restrict__ fixed, double dt, int drift) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (fixed && fixed[i]) {
+    vel[i] = 0.0;
+    vel[n + i] = 0.0;
+    vel[2 * n + i] = 0.0;
+    return;
+  }
+  const double a = 0.5 * dt * kAcc / mass[i];
+  const int s = sv.sys_of[i];
+  const double* H = sv.H + 9 * s;
+  for (int k = 0; k < 3; ++k) {
+    double v = vel[k * n + i] + a * force[k * n + i];
+    vel[k * n + i] = v;
+    if (drift) {
+      double x = pos[k * n + i] + dt * v;
+      if (sv.per[k] && sv.ortho[s]) {
+        const double L = H[4 * k];
+        x = x >= L ? x - L : (x < 0.0 ? x + L : x);
+      }
+      pos[k * n + i] = x;
+    }
+  }
+}
+
+hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* vel,
+                             const double* force, const double* mass, const uint8_t* fixed,
+                             double dt, bool drift, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kick_drift, dim3((n + 255) / 256), dim3(256), 0, s, n, sv, pos, vel, force,
+                     mass, fixed, dt, drift ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void k_check_finite(int n, const double* __restrict__ f, int32_t* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = f[i], b = f[n + i], c = f[2 * n + i];
+  if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3((n + 255) / 256), dim3(256), 0, s, n, force, flag);
+  return hipGetLastError();
+}
+
+}  // namespace ap

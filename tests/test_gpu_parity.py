@@ -1,0 +1,114 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle,
+element by element, at oracle-sized inputs that span several tiles and a
+ragged tail.  FP64 mode: max |dF| / rms(F) <= 1e-10, |dE|/|E| <= 1e-10;
+neighbour lists and the ACE-active list bit-exact."""
+import numpy as np
+import pytest
+
+from gpu_helpers import run_force
+from oracle.ap import APOracle
+from oracle.geometry import Systems
+from oracle.switching import ace_list as o_ace_list
+from oracle.switching import lambda_of
+from paper_2505_12958_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _wl(name):
+    if name == "bulk2000":
+        return w.workload(1)
+    if name == "wslab10":
+        return w.workload(3, scale=10)
+    if name == "cuslab8":
+        return w.workload(2, scale=8)
+    if name == "batch6":
+        return w.workload(4, scale=6)
+    raise KeyError(name)
+
+
+_CACHE = {}
+
+
+def oracle(name):
+    if name not in _CACHE:
+        wl = _wl(name)
+        S = Systems.from_workload(wl)
+        lam = lambda_of(wl.pos, wl.rule)
+        out = APOracle(wl.eam, wl.ace).evaluate(S, lam)
+        _CACHE[name] = (wl, out)
+    return _CACHE[name]
+
+
+CASES = ["bulk2000", "wslab10", "cuslab8", "batch6"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_neighbour_lists_bit_exact(name):
+    wl, ref = oracle(name)
+    g = run_force(wl, with_ace=False)
+    assert len(g["nl"]) == wl.n_atoms
+    for i in range(wl.n_atoms):
+        assert np.array_equal(g["nl"][i], ref["nl"][i][0]), i
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_switching_and_ace_list(name):
+    wl, ref = oracle(name)
+    g = run_force(wl, with_ace=False, with_eam=True)
+    assert np.abs(g["lam"] - ref["lam"]).max() <= 1e-12
+    assert np.array_equal(g["ace_list"], o_ace_list(ref["lam"]))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp64_energy_forces_virial(name):
+    wl, ref = oracle(name)
+    g = run_force(wl)
+    F, Fr = g["forces"], ref["forces"]
+    rms = np.sqrt(np.mean(Fr ** 2))
+    assert np.abs(F - Fr).max() / rms <= TOL
+    assert np.abs(g["e_atom"] - ref["e_atom"]).max() <= TOL * np.abs(ref["e_atom"]).max()
+    assert np.all(np.abs(g["e_sys"] - ref["e_sys"]) <= TOL * np.abs(ref["e_sys"]))
+    dW = np.abs(g["virial"] - ref["virial"]).max()
+    assert dW <= TOL * np.abs(ref["virial"]).max()
+
+
+@pytest.mark.parametrize("name", ["bulk2000", "wslab10"])
+def test_fp64_lambda_limits(name):
+    wl, _ = oracle(name)
+    n = wl.n_atoms
+    S = Systems.from_workload(wl)
+    for lam in (np.zeros(n), np.ones(n)):
+        ref = APOracle(wl.eam, wl.ace).evaluate(S, lam)
+        g = run_force(wl, lam=lam)
+        rms = np.sqrt(np.mean(ref["forces"] ** 2))
+        assert np.abs(g["forces"] - ref["forces"]).max() / rms <= TOL
+
+
+def test_fp64_bitwise_reproducible():
+    wl, _ = oracle("wslab10")
+    a = run_force(wl)
+    b = run_force(wl)
+    assert np.array_equal(a["forces"], b["forces"])
+    assert np.array_equal(a["e_atom"], b["e_atom"])
+    assert np.array_equal(a["virial"], b["virial"])
+
+
+def test_sum_of_forces_zero():
+    wl, _ = oracle("batch6")
+    g = run_force(wl)
+    F = g["forces"]
+    for s in range(wl.n_systems):
+        a, b = wl.sys_offset[s], wl.sys_offset[s + 1]
+        assert np.abs(F[a:b].sum(0)).max() <= 1e-11 * np.abs(F[a:b]).sum()
+
+
+def test_capacity_overflow_reports_needed():
+    from paper_2505_12958_amd import ap
+    wl, ref = oracle("bulk2000")
+    with pytest.raises(ap.APError) as e:
+        run_force(wl, capacity=32, with_ace=False)
+    assert e.value.status == ap.AP_ERR_NBR_CAPACITY
+    assert e.value.needed == max(len(x[0]) for x in ref["nl"])
