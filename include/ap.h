@@ -265,6 +265,39 @@ ap_status ap_step(ap_ctx* ctx, const ap_systems* sys, ap_md_state* st, int32_t n
  * clears the latch. */
 ap_status ap_check(ap_ctx* ctx, void* stream);
 
+/* Per-phase GPU timing with HIP events recorded on each call's stream around
+ * the kernels of a phase (AP_PHASE_ACE brackets exactly the ACE kernel
+ * launch).  ap_profile(ctx, 1) clears the totals and starts recording,
+ * ap_profile(ctx, 0) stops.  ap_profile_read synchronises the device and
+ * returns, for the first n phases, the accumulated milliseconds (ms[n]) and
+ * the number of timed launches (calls[n]); either pointer may be NULL. */
+enum {
+  AP_PHASE_NEIGHBORS = 0,
+  AP_PHASE_BLEND = 1,
+  AP_PHASE_EAM = 2,
+  AP_PHASE_ACE = 3,
+  AP_PHASE_ACE_GATHER = 4,
+  AP_PHASE_INDENTER = 5,
+  AP_PHASE_INTEGRATE = 6,
+  AP_PHASE_REDUCE = 7,
+  AP_N_PHASES = 8
+};
+ap_status ap_profile(ap_ctx* ctx, int32_t enable);
+ap_status ap_profile_read(ap_ctx* ctx, double* ms, int64_t* calls, int32_t n);
+
+/* Algorithmic work counts of the loaded model, by key:
+ *   "ace.flops_atom"     FLOPs per ACE-active atom of the coupling, folded
+ *                        contraction (both coefficient sets) and adjoint;
+ *   "ace.flops_contract" the folded-contraction part of ace.flops_atom;
+ *   "ace.flops_bond"     FLOPs per bond of the radial/harmonic basis, the A
+ *                        accumulation and the bond gradient;
+ *   "ace.nnz"            non-zeros of the folded coefficient matrices;
+ *   "ace.x_rows"         rows of the coupled vectors X_L summed over L;
+ *   "ace.a_size"         length of the atomic basis A;
+ *   "eam.flops_bond"     FLOPs per bond of the two EAM passes.
+ * Returns AP_ERR_ARG for an unknown key. */
+ap_status ap_info(const ap_ctx* ctx, const char* key, double* value);
+
 /* Library version string, e.g. "ap 0.1 gfx950". */
 const char* ap_version(void);
 

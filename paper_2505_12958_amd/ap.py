@@ -104,7 +104,10 @@ def lib():
         L.ap_reduce_energy.argtypes = [vp, C.POINTER(Systems), vp, vp, vp]
         L.ap_step.argtypes = [vp, C.POINTER(Systems), C.POINTER(MDState), i32, vp]
         L.ap_check.argtypes = [vp, vp]
-        for f in ("ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_eam_forces",
+        L.ap_profile.argtypes = [vp, i32]
+        L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
+        L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
+        for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_eam_forces",
                   "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -113,7 +116,8 @@ def lib():
 
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
-           "ap_check", "ap_version")
+           "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
+PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce")
 
 
 def _ptr(t):
@@ -289,6 +293,22 @@ class Context:
 
     def check(self):
         self._check(lib().ap_check(self.h, _stream()))
+
+    def profile(self, enable):
+        self._check(lib().ap_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase: (total_ms, timed_calls)} accumulated since profile(True)."""
+        n = len(PHASES)
+        ms = (C.c_double * n)()
+        calls = (C.c_int64 * n)()
+        self._check(lib().ap_profile_read(self.h, ms, calls, n))
+        return {PHASES[k]: (ms[k], calls[k]) for k in range(n)}
+
+    def info(self, key):
+        v = C.c_double()
+        self._check(lib().ap_info(self.h, key.encode(), C.byref(v)))
+        return v.value
 
 
 class MD:

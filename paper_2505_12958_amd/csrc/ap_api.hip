@@ -467,6 +467,20 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       (st = upload_owned(ctx, cx_ptr, &a.cx_ptr)) || (st = upload_owned(ctx, cx_col, &a.cx_col)) ||
       (st = upload_owned(ctx, cx_val, &a.cx_val)))
     return st;
+  {
+    double contract = 0, xrows = 0;
+    for (int L = 0; L <= Lmax; ++L) {
+      const int w = 2 * L + 1;
+      const int nnzL = cx_ptr[a.cx_off[L] + a.nrow[L]] - cx_ptr[a.cx_off[L]];
+      contract += 4.0 * nnzL * w + 4.0 * a.nrow[L] * w;
+      xrows += a.nrow[L];
+    }
+    ctx->flops_contract = contract;
+    ctx->flops_atom = contract + 3.0 * xb_c.size() + 5.0 * ad_c.size();
+    ctx->nnz = (double)cx_col.size();
+    ctx->x_rows = xrows;
+    ctx->flops_bond = 12.0 * K + 6.0 * a.nnl * K + 6.0 * nA + 20.0 * nlm + 40.0;
+  }
   ctx->ace_lds = ace_lds_bytes(a, ctx->precision);
   if (ctx->ace_lds > 160 * 1024) return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for LDS");
   return AP_OK;
@@ -595,6 +609,7 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
       (st = ensure(ctx, ctx->scan_tmp, 4 * ((size_t)std::max<int64_t>(nc, N) / 4096 + 2))))
     return st;
   int32_t* flags = (int32_t*)ctx->flags.p;
+  PhaseTimer timer(ctx, AP_PHASE_NEIGHBORS, s);
   if (needed_capacity) AP_HIP(launch_fill_i32(flags, 0, 1, s));
   AP_HIP(launch_fill_i32((int32_t*)ctx->cell_count.p, 0, nc, s));
   AP_HIP(launch_bin(sv, pos, (int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_count.p, s));
@@ -642,6 +657,7 @@ ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap
       (st = ensure(ctx, ctx->scan_tmp, 4 * ((size_t)N / 4096 + 2))))
     return st;
   int32_t* flag = (int32_t*)ctx->e_tmp.p;
+  PhaseTimer timer(ctx, AP_PHASE_BLEND, s);
   AP_HIP(launch_blend((int32_t)N, pos, *rule, lambda, flag, s));
   AP_HIP(launch_compact((int32_t)N, flag, ace_list, n_ace, (int32_t*)ctx->scan_tmp.p, s));
   return AP_OK;
@@ -650,6 +666,7 @@ ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap
 static ap_status reduce_into(Ctx* ctx, const SysView& sv, const double* vals, int m, double* out,
                              bool accumulate, hipStream_t s) {
   ap_status st;
+  PhaseTimer timer(ctx, AP_PHASE_REDUCE, s);
   if ((st = scratch_reduce(ctx, m))) return st;
   AP_HIP(launch_reduce(sv, ctx->sys.n_chunks, (const int64_t*)ctx->sys.chunk_lo_d.p,
                        (const int64_t*)ctx->sys.chunk_hi_d.p, (const int32_t*)ctx->sys.sys_chunk_d.p,
@@ -677,8 +694,11 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     return st;
   const bool acc = flags == AP_ACCUMULATE;
   double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
+  {
+  PhaseTimer timer(ctx, AP_PHASE_EAM, s);
   AP_HIP(launch_eam(*ctx, sv, pos, nl->nbr, nl->count, (int32_t)N, lambda, (double*)ctx->wfp.p,
                     (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom, force, vir, acc, s));
+  }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
 }
@@ -711,11 +731,18 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if (!acc) AP_HIP(launch_fill_f64(e_atom, 0.0, N, s));
   if (vir) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
-  AP_HIP(launch_ace(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda, ace_list,
-                    n_ace, (int32_t*)ctx->ace_row.p, (int32_t*)ctx->ace_counter.p, ctx->pair_g.p,
-                    e_atom, vir, s));
-  AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, nl->rev, nl->capacity,
-                           (const int32_t*)ctx->ace_row.p, ctx->pair_g.p, force, acc, s));
+  AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
+  {
+    PhaseTimer timer(ctx, AP_PHASE_ACE, s);
+    AP_HIP(launch_ace(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda, ace_list,
+                      n_ace, (int32_t*)ctx->ace_row.p, (int32_t*)ctx->ace_counter.p, ctx->pair_g.p,
+                      e_atom, vir, s));
+  }
+  {
+    PhaseTimer timer(ctx, AP_PHASE_ACE_GATHER, s);
+    AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, nl->rev, nl->capacity,
+                             (const int32_t*)ctx->ace_row.p, ctx->pair_g.p, force, acc, s));
+  }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
 }
@@ -737,6 +764,7 @@ ap_status ap_indenter(ap_ctx* c, const ap_systems* sys, const double* pos, const
   const bool want = e_ind || load;
   if (want && (st = ensure(ctx, ctx->ind_atom, 16 * (size_t)N + 64))) return st;
   double* e2 = want ? (double*)ctx->ind_atom.p : nullptr;
+  PhaseTimer timer(ctx, AP_PHASE_INDENTER, s);
   AP_HIP(launch_indenter((int32_t)N, pos, fixed, centre, R, K, dir, force, e2, s));
   if (want) {
     double* out = (double*)ctx->ind_atom.p + 2 * N;
@@ -828,18 +856,78 @@ ap_status ap_step(ap_ctx* c, const ap_systems* sys, ap_md_state* st, int32_t n_s
     if ((r = force_eval(ctx, sys, st, s))) return r;
   }
   for (int step = 0; step < n_steps; ++step) {
-    AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed, st->dt,
-                             true, s));
+    {
+      PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
+      AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed,
+                               st->dt, true, s));
+    }
     for (int k = 0; k < 3; ++k) st->ind_centre[k] += st->dt * st->ind_vel[k];
     if ((r = force_eval(ctx, sys, st, s))) return r;
-    AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed, st->dt,
-                             false, s));
+    {
+      PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
+      AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed,
+                               st->dt, false, s));
+    }
     if (st->check_every > 0 && (step + 1) % st->check_every == 0) {
       AP_HIP(launch_check_finite((int32_t)N, st->force, (int32_t*)ctx->flags.p + 1, s));
       if ((r = ap_check(c, s))) return r;
     }
   }
   if (st->e_sys && (r = ap_reduce_energy(c, sys, st->e_atom, st->e_sys, s))) return r;
+  return AP_OK;
+}
+
+static void prof_drain(Ctx* ctx) {
+  for (auto& e : ctx->evs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ctx->prof_ms[e.phase] += ms;
+      ctx->prof_calls[e.phase] += 1;
+    }
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  ctx->evs.clear();
+}
+
+ap_status ap_profile(ap_ctx* c, int32_t enable) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  prof_drain(ctx);
+  if (enable) {
+    for (int k = 0; k < AP_N_PHASES; ++k) {
+      ctx->prof_ms[k] = 0;
+      ctx->prof_calls[k] = 0;
+    }
+  }
+  ctx->prof = enable != 0;
+  return AP_OK;
+}
+
+ap_status ap_profile_read(ap_ctx* c, double* ms, int64_t* calls, int32_t n) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (n < 0 || n > AP_N_PHASES) return fail(ctx, AP_ERR_ARG, "n must be in [0, AP_N_PHASES]");
+  prof_drain(ctx);
+  for (int k = 0; k < n; ++k) {
+    if (ms) ms[k] = ctx->prof_ms[k];
+    if (calls) calls[k] = ctx->prof_calls[k];
+  }
+  return AP_OK;
+}
+
+ap_status ap_info(const ap_ctx* c, const char* key, double* value) {
+  const Ctx* ctx = (const Ctx*)c;
+  if (!ctx || !key || !value) return fail(nullptr, AP_ERR_ARG, "ctx/key/value is NULL");
+  const std::string k(key);
+  if (k == "ace.flops_atom") *value = ctx->flops_atom;
+  else if (k == "ace.flops_contract") *value = ctx->flops_contract;
+  else if (k == "ace.flops_bond") *value = ctx->flops_bond;
+  else if (k == "ace.nnz") *value = ctx->nnz;
+  else if (k == "ace.x_rows") *value = ctx->x_rows;
+  else if (k == "ace.a_size") *value = ctx->ace.nA;
+  else if (k == "eam.flops_bond") *value = 80.0;
+  else return fail(const_cast<Ctx*>(ctx), AP_ERR_ARG, "unknown info key");
   return AP_OK;
 }
 

@@ -117,6 +117,33 @@ struct Ctx {
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
   size_t ace_lds = 0;
+  // algorithmic work counts (ap_info)
+  double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
+  // per-phase event timing (ap_profile)
+  bool prof = false;
+  struct Ev { int phase; hipEvent_t a, b; };
+  std::vector<Ev> evs;
+  double prof_ms[AP_N_PHASES] = {0};
+  int64_t prof_calls[AP_N_PHASES] = {0};
+};
+
+// Records a HIP event pair around a phase when profiling is on.
+struct PhaseTimer {
+  Ctx* c;
+  int ph;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseTimer(Ctx* c_, int ph_, hipStream_t s_) : c(c_), ph(ph_), s(s_) {
+    if (c->prof && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, s);
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) == hipSuccess) {
+      hipEventRecord(b, s);
+      c->evs.push_back({ph, a, b});
+    }
+  }
 };
 
 // error helpers (ap_api.hip)
@@ -167,6 +194,7 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
                       bool accumulate, hipStream_t s);
 // ACE (k_ace.hip)
 size_t ace_lds_bytes(const AceDev& a, int precision);
+hipError_t launch_ace_reset(int32_t* counter, hipStream_t s);
 hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,

@@ -226,14 +226,17 @@ hipError_t launch_ace_rows(int32_t n_atoms, const int32_t* ace_list, const int32
   return hipGetLastError();
 }
 
+hipError_t launch_ace_reset(int32_t* counter, hipStream_t s) {
+  return launch_fill_i32(counter, 0, 1, s);
+}
+
 hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
                       hipStream_t s) {
   (void)ace_row;
-  hipError_t e = launch_fill_i32(counter, 0, 1, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   int dev = 0, n_cu = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
