@@ -266,8 +266,8 @@ ap_status ap_step(ap_ctx* ctx, const ap_systems* sys, ap_md_state* st, int32_t n
 ap_status ap_check(ap_ctx* ctx, void* stream);
 
 /* Per-phase GPU timing with HIP events recorded on each call's stream around
- * the kernels of a phase (AP_PHASE_ACE brackets exactly the ACE kernel
- * launch).  ap_profile(ctx, 1) clears the totals and starts recording,
+ * the kernels of a phase (AP_PHASE_ACE brackets exactly the launch of the
+ * kernel that does the ACE contraction).  ap_profile(ctx, 1) clears the totals and starts recording,
  * ap_profile(ctx, 0) stops.  ap_profile_read synchronises the device and
  * returns, for the first n phases, the accumulated milliseconds (ms[n]) and
  * the number of timed launches (calls[n]); either pointer may be NULL. */
@@ -280,7 +280,8 @@ enum {
   AP_PHASE_INDENTER = 5,
   AP_PHASE_INTEGRATE = 6,
   AP_PHASE_REDUCE = 7,
-  AP_N_PHASES = 8
+  AP_PHASE_ACE_BOND = 8, /* mixed path: bond basis and bond-gradient kernels */
+  AP_N_PHASES = 9
 };
 ap_status ap_profile(ap_ctx* ctx, int32_t enable);
 ap_status ap_profile_read(ap_ctx* ctx, double* ms, int64_t* calls, int32_t n);

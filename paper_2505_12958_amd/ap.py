@@ -117,7 +117,8 @@ def lib():
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
            "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
-PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce")
+PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce",
+          "ace_bond")
 
 
 def _ptr(t):

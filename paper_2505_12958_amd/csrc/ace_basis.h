@@ -44,31 +44,36 @@ __device__ __forceinline__ void cheb_basis(int K, T rc, T r, T* g, T* dg) {
   const T s = (T)2 / rc;
   g[0] = fc;
   dg[0] = dfc;
-  if (K > 1) {
-    g[1] = x * fc;
-    dg[1] = d1 * s * fc + x * dfc;
-  }
-  for (int k = 2; k < K; ++k) {
+  g[1] = x * fc;
+  dg[1] = d1 * s * fc + x * dfc;
+#pragma unroll
+  for (int k = 2; k < kMaxK; ++k) {
     const T t2 = (T)2 * x * t1 - t0;
     const T d2 = (T)2 * t1 + (T)2 * x * d1 - d0;
     g[k] = t2 * fc;
     dg[k] = d2 * s * fc + t2 * dfc;
     t0 = t1; t1 = t2; d0 = d1; d1 = d2;
   }
+  (void)K;
 }
 
 // Q[l][m] = d^m P_l / dz^m for 0 <= m <= l+1 (zero for m = l+1), l <= lmax
 template <typename T>
 __device__ __forceinline__ void legendre_derivs(int lmax, T z, T Q[kMaxL + 1][kMaxL + 2]) {
-  for (int m = 0; m <= lmax; ++m) {
+  (void)lmax;
+#pragma unroll
+  for (int m = 0; m <= kMaxL; ++m) {
     T dfact = 1;
+#pragma unroll
     for (int k = 1; k <= 2 * m - 1; k += 2) dfact *= (T)k;
     Q[m][m] = dfact;
-    if (m + 1 <= lmax) Q[m + 1][m] = (T)(2 * m + 1) * z * dfact;
-    for (int l = m + 2; l <= lmax; ++l)
+    if (m + 1 <= kMaxL) Q[m + 1][m] = (T)(2 * m + 1) * z * dfact;
+#pragma unroll
+    for (int l = m + 2; l <= kMaxL; ++l)
       Q[l][m] = ((T)(2 * l - 1) * z * Q[l - 1][m] - (T)(l + m - 1) * Q[l - 2][m]) / (T)(l - m);
   }
-  for (int l = 0; l <= lmax; ++l) Q[l][l + 1] = 0;
+#pragma unroll
+  for (int l = 0; l <= kMaxL; ++l) Q[l][l + 1] = 0;
 }
 
 // Y[lm] (lm = l*l + l + m) of the unit vector (x, y, z); with dY != nullptr
@@ -81,12 +86,15 @@ __device__ __forceinline__ void real_ylm(int lmax, const double* ynorm, T x, T y
   T C[kMaxL + 1], S[kMaxL + 1];
   C[0] = 1;
   S[0] = 0;
-  for (int m = 1; m <= lmax; ++m) {
+#pragma unroll
+  for (int m = 1; m <= kMaxL; ++m) {
     C[m] = x * C[m - 1] - y * S[m - 1];
     S[m] = x * S[m - 1] + y * C[m - 1];
   }
   const T ir = (T)1 / r;
-  for (int l = 0; l <= lmax; ++l) {
+#pragma unroll
+  for (int l = 0; l <= kMaxL; ++l) {
+    if (l > lmax) break;
     const int c0 = l * l + l;
     {
       const T nrm = (T)ynorm[c0];
@@ -99,6 +107,7 @@ __device__ __forceinline__ void real_ylm(int lmax, const double* ynorm, T x, T y
         dY[c0][2] = (gz - ug * z) * ir;
       }
     }
+#pragma unroll
     for (int m = 1; m <= l; ++m) {
       const T nrm = (T)ynorm[c0 + m];
       Y[c0 + m] = nrm * Q[l][m] * C[m];
@@ -132,18 +141,22 @@ __device__ __forceinline__ void ylm_contract(int lmax, const double* ynorm, T x,
   T C[kMaxL + 1], S[kMaxL + 1];
   C[0] = 1;
   S[0] = 0;
-  for (int m = 1; m <= lmax; ++m) {
+#pragma unroll
+  for (int m = 1; m <= kMaxL; ++m) {
     C[m] = x * C[m - 1] - y * S[m - 1];
     S[m] = x * S[m - 1] + y * C[m - 1];
   }
   T sb = 0, gx = 0, gy = 0, gz = 0;
-  for (int l = 0; l <= lmax; ++l) {
+#pragma unroll
+  for (int l = 0; l <= kMaxL; ++l) {
+    if (l > lmax) break;
     const int c0 = l * l + l;
     {
       const T nrm = (T)ynorm[c0];
       sb += b[c0] * nrm * Q[l][0];
       gz += a[c0] * nrm * Q[l][1];
     }
+#pragma unroll
     for (int m = 1; m <= l; ++m) {
       const T nrm = (T)ynorm[c0 + m];
       const T ap = a[c0 + m], am = a[c0 - m];

@@ -482,7 +482,168 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     ctx->flops_bond = 12.0 * K + 6.0 * a.nnl * K + 6.0 * nA + 20.0 * nlm + 40.0;
   }
   ctx->ace_lds = ace_lds_bytes(a, ctx->precision);
-  if (ctx->ace_lds > 160 * 1024) return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for LDS");
+  if (ctx->precision == AP_PREC_FP64) {
+    if (ctx->ace_lds > 160 * 1024) return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for LDS");
+    return AP_OK;
+  }
+
+  // ---- mixed path: block-sparse split-bf16 tiles, channel groups
+  MixDev& x = ctx->mix;
+  x.n_max = nmax; x.l_max = lmax; x.K = K; x.nlm = nlm; x.nA = nA; x.nnl = a.nnl;
+  x.apad = nA | 1;
+  x.L_max = Lmax;
+  x.rc = m->r_c;
+  x.Wf = a.Wf;
+  x.ynorm = a.ynorm;
+  double mfma_flops = 0;
+  static const int kRtwMax[2 * kMaxL + 1] = {4, 5, 6, 6, 5, 4, 3, 2, 2};  // = kernel tiling
+  std::vector<int32_t> bt_ptr, bt_kt, bt_idx, grp_pat, pat_hdr;
+  std::vector<int4> grp_mem;
+  std::vector<CgEnt> pat_ent;
+  std::vector<float> pat_coef;
+  auto rule = [](int m1, int m2, int M) {
+    return ((M < 0) == ((m1 < 0) != (m2 < 0))) &&
+           (std::abs(M) == std::abs(m1) + std::abs(m2) || std::abs(M) == std::abs(std::abs(m1) - std::abs(m2)));
+  };
+  std::vector<uint4> ctile;
+  std::map<std::tuple<int, int, int>, int> pat_id;
+  size_t big = (size_t)4 * 64 * (a.nnl + nlm) * 4;
+  auto bf16_rne = [](float f) -> uint16_t {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  };
+  auto bf16_to_f = [](uint16_t b) -> float {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+  };
+  for (int L = 0; L <= Lmax; ++L) {
+    MixL& P = x.lv[L];
+    const int w = 2 * L + 1;
+    P.nrow = a.nrow[L];
+    P.nrow16 = (P.nrow + 15) / 16 * 16;
+    P.nch = nch[L];
+    P.arow = a.has_arow[L];
+    const int kpad = (P.nrow + 31) / 32 * 32;
+    P.kt = kpad / 32;
+    P.kstr = kpad + 8;
+    P.ct = (8 * w + 15) / 16;
+    P.rt = 2 * P.nrow16 / 16;
+    P.zstr = 8 * w + 1;
+    if ((P.nrow16 / 16 + 3) / 4 > kRtwMax[L] || P.ct > L + 1)
+      return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's register tiling");
+    big = std::max(big, (size_t)P.ct * 16 * P.kstr * 2 * 2);
+    big = std::max(big, (size_t)P.nrow * P.zstr * 4);
+    // dense folded matrix of this L (both sets)
+    std::vector<double> D((size_t)P.nrow * P.nrow * 2, 0.0);
+    for (auto& kv : Cm[L]) {
+      D[((size_t)kv.first.first * P.nrow + kv.first.second) * 2] = kv.second.first;
+      D[((size_t)kv.first.first * P.nrow + kv.first.second) * 2 + 1] = kv.second.second;
+    }
+    P.bt0 = (int32_t)bt_ptr.size();
+    for (int rt = 0; rt < P.rt; ++rt) {
+      bt_ptr.push_back((int32_t)bt_kt.size());
+      for (int kt = 0; kt < P.kt; ++kt) {
+        double v[16][32];
+        bool any = false;
+        for (int i = 0; i < 16; ++i)
+          for (int kk = 0; kk < 32; ++kk) {
+            const int r = rt * 16 + i, k = kt * 32 + kk;
+            const int p = r / P.nrow16, rr = r % P.nrow16;
+            double val = 0.0;
+            if (rr < P.nrow && k < P.nrow) val = D[((size_t)rr * P.nrow + k) * 2 + p];
+            v[i][kk] = val;
+            any = any || val != 0.0;
+          }
+        if (!any) continue;
+        mfma_flops += 3.0 * 2.0 * 16 * 16 * 32 * P.ct / 8.0;  // per atom (tile of 8 atoms)
+        const int idx = (int)(ctile.size() / 128);
+        bt_kt.push_back(kt);
+        bt_idx.push_back(idx);
+        ctile.resize(ctile.size() + 128);
+        for (int lane = 0; lane < 64; ++lane) {
+          uint16_t hi[8], lo[8];
+          for (int j = 0; j < 8; ++j) {
+            const double val = v[lane % 16][8 * (lane / 16) + j];
+            hi[j] = bf16_rne((float)val);
+            lo[j] = bf16_rne((float)(val - (double)bf16_to_f(hi[j])));
+          }
+          uint4 h4, l4;
+          memcpy(&h4, hi, 16);
+          memcpy(&l4, lo, 16);
+          ctile[(size_t)idx * 128 + lane] = h4;
+          ctile[(size_t)idx * 128 + 64 + lane] = l4;
+        }
+      }
+    }
+    bt_ptr.push_back((int32_t)bt_kt.size());
+    // channel groups of equal (la, lb)
+    std::map<std::pair<int, int>, std::vector<int4>> by_pat;
+    for (auto& kv : chan) {
+      if (std::get<0>(kv.first) != L) continue;
+      const int xa = std::get<1>(kv.first), xb = std::get<2>(kv.first);
+      const int na = xa / lp1, la = xa % lp1, nb = xb / lp1, lb = xb % lp1;
+      by_pat[{la, lb}].push_back(make_int4(kv.second, na * nlm + la * la, nb * nlm + lb * lb, 0));
+    }
+    P.grp0 = (int32_t)grp_pat.size();
+    for (auto& kv : by_pat) {
+      const int la = kv.first.first, lb = kv.first.second;
+      auto key = std::make_tuple(la, lb, L);
+      if (!pat_id.count(key)) {
+        const auto& C = cgcache[key];
+        const int e0 = (int)pat_ent.size();
+        const int w1 = 2 * la + 1, w2 = 2 * lb + 1;
+        for (int M = 0; M < w; ++M)
+          for (int p = 0; p < w1; ++p)
+            for (int q = 0; q < w2; ++q) {
+              const double c = C[((size_t)p * w2 + q) * w + M];
+              if (c != 0.0) pat_ent.push_back(CgEnt{(int8_t)p, (int8_t)q, (int8_t)M, 0, (float)c});
+            }
+        // coefficients over the selection-rule superset, (m1, m2, M) order
+        const int c0 = (int)pat_coef.size();
+        for (int p = 0; p < w1; ++p)
+          for (int q = 0; q < w2; ++q)
+            for (int M = 0; M < w; ++M) {
+              const double c = C[((size_t)p * w2 + q) * w + M];
+              if (rule(p - la, q - lb, M - L)) {
+                pat_coef.push_back((float)c);
+              } else if (c != 0.0) {
+                return fail(ctx, AP_ERR_ARG, "coupling coefficient outside the selection rule");
+              }
+            }
+        (void)e0;
+        pat_id[key] = (int)pat_hdr.size() / 5;
+        pat_hdr.insert(pat_hdr.end(), {la, lb, L, la * 45 + lb * 9 + L, c0});
+      }
+      const int pid = pat_id[key];
+      const auto& mem = kv.second;
+      for (size_t g = 0; g < mem.size(); g += 8) {
+        grp_pat.push_back(pid);
+        for (size_t q = g; q < g + 8; ++q)
+          grp_mem.push_back(q < mem.size() ? mem[q] : make_int4(-1, 0, 0, 0));
+      }
+    }
+    P.ngrp = (int32_t)grp_pat.size() - P.grp0;
+  }
+  x.big_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16) * 4 + 15) / 16 * 16);
+  x.big_bytes = (int32_t)big;
+  if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
+    return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");
+  if ((st = upload_owned(ctx, bt_ptr, &x.bt_ptr)) || (st = upload_owned(ctx, bt_kt, &x.bt_kt)) ||
+      (st = upload_owned(ctx, bt_idx, &x.bt_idx)) || (st = upload_owned(ctx, ctile, &x.ctile)) ||
+      (st = upload_owned(ctx, grp_pat, &x.grp_pat)) || (st = upload_owned(ctx, grp_mem, &x.grp_mem)) ||
+      (st = upload_owned(ctx, pat_hdr, &x.pat_hdr)) || (st = upload_owned(ctx, pat_ent, &x.pat_ent)) ||
+      (st = upload_owned(ctx, pat_coef, &x.pat_coef)))
+    return st;
+  {
+    std::vector<MixL> lv(x.lv, x.lv + Lmax + 1);
+    if ((st = upload_owned(ctx, lv, &x.lv_d))) return st;
+  }
+  ctx->mix_tiles = (double)bt_kt.size();
+  ctx->mix_mfma_flops = mfma_flops;
   return AP_OK;
 }
 
@@ -578,7 +739,8 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
-                    &ctx->ace_rows_list, &ctx->partials, &ctx->flags, &ctx->ind_atom})
+                    &ctx->ace_rows_list, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
+                    &ctx->mix_om, &ctx->mix_phi})
     release(*b);
   delete ctx;
   return AP_OK;
@@ -711,7 +873,6 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
   if (!ctx->has_ace) return fail(ctx, AP_ERR_ARG, "context has no ACE model");
   if (flags > 1u) return fail(ctx, AP_ERR_ARG, "flags must be AP_OVERWRITE or AP_ACCUMULATE");
-  if (ctx->precision != AP_PREC_FP64) return fail(ctx, AP_ERR_UNSUPPORTED, "mixed ACE path not built");
   if (ace_list && !n_ace) return fail(ctx, AP_ERR_ARG, "n_ace is NULL");
   hipStream_t s = (hipStream_t)stream;
   ap_status st;
@@ -732,11 +893,25 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if (vir) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
   AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
-  {
+  if (ctx->precision == AP_PREC_FP64) {
     PhaseTimer timer(ctx, AP_PHASE_ACE, s);
     AP_HIP(launch_ace(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda, ace_list,
                       n_ace, (int32_t*)ctx->ace_row.p, (int32_t*)ctx->ace_counter.p, ctx->pair_g.p,
                       e_atom, vir, s));
+  } else {
+    const MixDev& mx = ctx->mix;
+    const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
+    if ((st = ensure(ctx, ctx->mix_A, 4 * rows * mx.nA)) ||
+        (st = ensure(ctx, ctx->mix_om, 8 * rows * mx.nA)) ||
+        (st = ensure(ctx, ctx->mix_phi, 8 * rows)))
+      return st;
+    for (int phase = 0; phase < 3; ++phase) {
+      PhaseTimer timer(ctx, phase == 1 ? AP_PHASE_ACE : AP_PHASE_ACE_BOND, s);
+      AP_HIP(launch_ace_mixed(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda,
+                              ace_list, n_ace, (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p,
+                              (float*)ctx->mix_A.p, (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p,
+                              e_atom, vir, s, phase));
+    }
   }
   {
     PhaseTimer timer(ctx, AP_PHASE_ACE_GATHER, s);
@@ -927,6 +1102,8 @@ ap_status ap_info(const ap_ctx* c, const char* key, double* value) {
   else if (k == "ace.x_rows") *value = ctx->x_rows;
   else if (k == "ace.a_size") *value = ctx->ace.nA;
   else if (k == "eam.flops_bond") *value = 80.0;
+  else if (k == "ace.mfma_tiles") *value = ctx->mix_tiles;
+  else if (k == "ace.mfma_flops_atom") *value = ctx->mix_mfma_flops;
   else return fail(const_cast<Ctx*>(ctx), AP_ERR_ARG, "unknown info key");
   return AP_OK;
 }

@@ -82,6 +82,40 @@ struct AceDev {
   int32_t max_xsize;        // max_L nrow*(2L+1)
 };
 
+// ---- mixed-precision ACE model: per-L tiling, block-sparse bf16 tiles,
+// channel groups of equal (l_a, l_b) with their coupling entries
+struct CgEnt {
+  int8_t m1, m2, M, pad;
+  float c;
+};
+
+struct MixL {
+  int32_t nrow, nrow16, nch, arow;  // rows of X_L, padded to 16, channel rows, has A rows
+  int32_t rt, ct, kt;               // row tiles (both sets), column tiles, k tiles
+  int32_t kstr, zstr;               // LDS strides of the operand (bf16) and of Z (floats)
+  int32_t grp0, ngrp;               // channel groups of this L
+  int32_t bt0;                      // first row-tile pointer of this L in bt_ptr
+};
+
+struct MixDev {
+  int32_t n_max, l_max, K, nlm, nA, apad, nnl, L_max;
+  double rc;
+  const float* Wf;
+  const double* ynorm;
+  MixL lv[2 * kMaxL + 1];   // host copy
+  const MixL* lv_d;         // device copy (indexed by L in the kernel)
+  const int32_t* bt_ptr;   // per L: rt + 1 offsets into bt_kt / bt_idx
+  const int32_t* bt_kt;    // k tile of each stored tile
+  const int32_t* bt_idx;   // tile data index
+  const uint4* ctile;      // (2 * idx + split) * 64 + lane: 8 bf16 per lane
+  const int32_t* grp_pat;  // pattern of each group
+  const int4* grp_mem;     // 8 members per group: {row, A offset of a, A offset of b, 0}
+  const int32_t* pat_hdr;  // 5 ints per pattern: la, lb, L, switch key, first coefficient
+  const CgEnt* pat_ent;
+  const float* pat_coef;   // coefficients per pattern over the selection-rule superset
+  int32_t big_off, big_bytes;  // LDS layout
+};
+
 struct Buffer {
   void* p = nullptr;
   size_t bytes = 0;
@@ -107,6 +141,7 @@ struct Ctx {
   bool has_eam = false, has_ace = false;
   TableDev phi{}, rho{}, F{};
   AceDev ace{};
+  MixDev mix{};
   std::vector<Buffer> owned;            // model tables
   SysCache sys;
   // scratch, grown on demand
@@ -114,11 +149,14 @@ struct Ctx {
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
   Buffer ace_row, pair_g, ace_counter, ace_rows_list;
+  Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
   size_t ace_lds = 0;
   // algorithmic work counts (ap_info)
   double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
+  double mix_tiles = 0;        // stored 16x32 coefficient tiles (mixed path)
+  double mix_mfma_flops = 0;   // executed MFMA FLOPs per ACE atom (3 split products)
   // per-phase event timing (ap_profile)
   bool prof = false;
   struct Ev { int phase; hipEvent_t a, b; };
@@ -200,6 +238,14 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
                       hipStream_t s);
+// phase 0: bond basis -> A; 1: coupling/contraction/adjoint -> om, phi;
+// 2: embedding, bond gradients, virial
+hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                            const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
+                            const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
+                            float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
+                            double* e_atom, double* vir_atom, hipStream_t s, int phase);
+size_t ace_mixed_lds_bytes(const MixDev& m);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
                              const void* pair_g, double* force, bool accumulate, hipStream_t s);

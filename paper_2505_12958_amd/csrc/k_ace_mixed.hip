@@ -1,0 +1,630 @@
+// ACE part of the AP force, mixed-precision path.
+//
+// One workgroup (256 threads, 4 wavefronts, one per SIMD) evaluates a tile of 8 ACE-active
+// atoms taken from a global counter (persistent loop), entirely on chip:
+//
+//  1. bond basis in FP32 from the FP64 minimum-image displacement; the
+//     atomic basis A_nlm of the 8 atoms is accumulated in LDS;
+//  2. per coupled rank L:
+//     a. coupling X_L = [AA_{c,M} | A_{n,L,M} | 1] for the 8 atoms (VALU;
+//        one lane per (channel, atom), channels grouped by (l_a, l_b) so the
+//        Clebsch-Gordan entries are wavefront-uniform), written to LDS as a
+//        bf16 hi/lo split (x = hi + lo to ~16 bits);
+//     b. folded contraction Z_L = C_L X_L for both coefficient sets with
+//        v_mfma_f32_16x16x32_bf16: only non-zero 16x32 tiles of C_L are
+//        stored (pre-split into bf16 hi/lo), each product taken as
+//        hi*hi + hi*lo + lo*hi with FP32 accumulation;
+//     c. Z_L of each set goes to LDS (over the dead X_L) and the adjoint
+//        dphi/dA = (dX_L/dA)^T Z_L is gathered per (channel, atom) and added
+//        to the atom's gradient; phi = X.Z/2 is accumulated on the way;
+//  3. embedding E = phi1 + sqrt(|phi2| + 1e-6) and its derivative in FP64;
+//  4. per-bond gradients g_ij (FP32) and the atom's virial (FP64 sums).
+#include "ace_basis.h"
+#include "ap_internal.h"
+#include "geom.h"
+#include "scan.h"
+
+namespace ap {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 8;
+constexpr int kMThreads = 256;
+constexpr int kMWaves = kMThreads / 64;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Values the compiler cannot prove uniform (loads next to stores) are made
+// wavefront-uniform explicitly so they live in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ MixL load_level(const MixL* p) {
+  MixL P = *p;
+  P.nrow = uni(P.nrow); P.nrow16 = uni(P.nrow16); P.nch = uni(P.nch); P.arow = uni(P.arow);
+  P.rt = uni(P.rt); P.ct = uni(P.ct); P.kt = uni(P.kt); P.kstr = uni(P.kstr); P.zstr = uni(P.zstr);
+  P.grp0 = uni(P.grp0); P.ngrp = uni(P.ngrp); P.bt0 = uni(P.bt0);
+  return P;
+}
+
+__device__ __forceinline__ CgEnt load_ent(const CgEnt* p) {
+  const int2 raw = *reinterpret_cast<const int2*>(p);
+  const int w0 = uni(raw.x);
+  CgEnt e;
+  e.m1 = (int8_t)(w0 & 0xff);
+  e.m2 = (int8_t)((w0 >> 8) & 0xff);
+  e.M = (int8_t)((w0 >> 16) & 0xff);
+  e.pad = 0;
+  e.c = __int_as_float(uni(raw.y));
+  return e;
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// GEMM of one L: accumulators of the wavefront's row tiles (rt = wave + 8 i)
+// for all column tiles.  X is read from LDS (column-major, k contiguous).
+template <int RTW, int CTN>
+__device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const __bf16* xh,
+                                           const __bf16* xl, f32x4 (&acc)[RTW][CTN], int wave,
+                                           int lane, int p) {
+  const int rt_set = P.nrow16 / 16;
+#pragma unroll
+  for (int i = 0; i < RTW; ++i)
+#pragma unroll
+    for (int c = 0; c < CTN; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int cur[RTW], end[RTW];
+#pragma unroll
+  for (int i = 0; i < RTW; ++i) {
+    const int rt = wave + kMWaves * i;
+    if (rt < rt_set) {
+      cur[i] = uni(m.bt_ptr[P.bt0 + p * rt_set + rt]);
+      end[i] = uni(m.bt_ptr[P.bt0 + p * rt_set + rt + 1]);
+    } else {
+      cur[i] = 0;
+      end[i] = 0;
+    }
+  }
+  const int col_l = lane & 15;
+  const int k_l = 8 * (lane >> 4);
+  for (int kt = 0; kt < P.kt; ++kt) {
+    uint4 ch[RTW], cl[RTW];
+    bool nz[RTW];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      nz[i] = cur[i] < end[i] && uni(m.bt_kt[cur[i]]) == kt;
+      if (nz[i]) {
+        const int idx = uni(m.bt_idx[cur[i]]);
+        ch[i] = m.ctile[(2 * (size_t)idx) * 64 + lane];
+        cl[i] = m.ctile[(2 * (size_t)idx + 1) * 64 + lane];
+        ++cur[i];
+        any = true;
+      }
+    }
+    if (!any) continue;
+#pragma unroll
+    for (int c = 0; c < CTN; ++c) {
+      if (c >= P.ct) break;
+      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
+      const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
+      const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
+#pragma unroll
+      for (int i = 0; i < RTW; ++i) {
+        if (!nz[i]) continue;
+        const bf16x8 ah = as_bf16x8(ch[i]), al = as_bf16x8(cl[i]);
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][c], 0, 0, 0);
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][c], 0, 0, 0);
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][c], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Write the accumulators of coefficient set p (rows [p*nrow16, (p+1)*nrow16))
+// as FP32 Z[row][col] into LDS.
+template <int RTW, int CTN>
+__device__ __forceinline__ void store_z(const MixL& P, const f32x4 (&acc)[RTW][CTN], float* Z,
+                                        int wave, int lane, int ncols) {
+  const int col_l = lane & 15;
+  const int r_l = 4 * (lane >> 4);
+#pragma unroll
+  for (int i = 0; i < RTW; ++i) {
+    const int rt = wave + kMWaves * i;
+    if (rt >= P.nrow16 / 16) continue;
+    const int row0 = rt * 16 + r_l;
+#pragma unroll
+    for (int c = 0; c < CTN; ++c) {
+      if (c >= P.ct) break;
+      const int col = c * 16 + col_l;
+      if (col >= ncols) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + q;
+        if (row >= 0 && row < P.nrow) Z[row * P.zstr + col] = acc[i][c][q];
+      }
+    }
+  }
+}
+
+// Selection rule of the real coupling coefficients C^{la lb L}_{m1 m2 M}
+// (l_a + l_b + L even): the M-type (cosine for M >= 0, sine for M < 0) is the
+// product of the m1- and m2-types and |M| is |m1| + |m2| or ||m1| - |m2||.
+// Every non-zero entry satisfies it; the library's coefficient table holds
+// one value per entry of this superset, in (m1, m2, M) order.
+__device__ constexpr int iabs_c(int v) { return v < 0 ? -v : v; }
+__device__ constexpr bool cg_rule(int m1, int m2, int M) {
+  return ((M < 0) == ((m1 < 0) != (m2 < 0))) &&
+         (iabs_c(M) == iabs_c(m1) + iabs_c(m2) || iabs_c(M) == iabs_c(iabs_c(m1) - iabs_c(m2)));
+}
+
+// Coupling of one (channel, atom) with compile-time pattern: register
+// indices are static and the coefficients come from uniform loads.
+// MODE 0: X[M] = sum c A_a[m1] A_b[m2].  MODE 1: additionally the adjoint
+// ga[m1] += c A_b[m2] Z[M], gb[m2] += c A_a[m1] Z[M].
+template <int LA, int LB, int L, int MODE>
+__device__ __forceinline__ void couple_static(const float* __restrict__ coef, const float* Aa,
+                                              const float* Ab, float* X, const float* Z, float* ga,
+                                              float* gb) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i <= 2 * LA; ++i) {
+#pragma unroll
+    for (int j = 0; j <= 2 * LB; ++j) {
+#pragma unroll
+      for (int q = 0; q <= 2 * L; ++q) {
+        if (cg_rule(i - LA, j - LB, q - L)) {
+          const float c = coef[k];
+          ++k;
+          const float ca = c * Aa[i];
+          X[q] = fmaf(ca, Ab[j], X[q]);
+          if (MODE == 1) {
+            const float cz = c * Z[q];
+            ga[i] = fmaf(cz, Ab[j], ga[i]);
+            gb[j] = fmaf(cz, Aa[i], gb[j]);
+          }
+        }
+      }
+    }
+  }
+}
+
+#define AP_CG_CASE(la, lb, LL)                                              \
+  case (la) * 45 + (lb) * 9 + (LL):                                         \
+    if constexpr (LL == L) couple_static<la, lb, LL, MODE>(coef, Aa, Ab, X, Z, ga, gb); \
+    break;
+
+template <int MODE, int L>
+__device__ __forceinline__ void couple_dispatch(int key, const float* __restrict__ coef,
+                                                const float* Aa, const float* Ab, float* X,
+                                                const float* Z, float* ga, float* gb) {
+  switch (key) {
+    AP_CG_CASE(0, 0, 0)
+    AP_CG_CASE(0, 1, 1)
+    AP_CG_CASE(0, 2, 2)
+    AP_CG_CASE(0, 3, 3)
+    AP_CG_CASE(0, 4, 4)
+    AP_CG_CASE(1, 0, 1)
+    AP_CG_CASE(1, 1, 0)
+    AP_CG_CASE(1, 1, 2)
+    AP_CG_CASE(1, 2, 1)
+    AP_CG_CASE(1, 2, 3)
+    AP_CG_CASE(1, 3, 2)
+    AP_CG_CASE(1, 3, 4)
+    AP_CG_CASE(1, 4, 3)
+    AP_CG_CASE(1, 4, 5)
+    AP_CG_CASE(2, 0, 2)
+    AP_CG_CASE(2, 1, 1)
+    AP_CG_CASE(2, 1, 3)
+    AP_CG_CASE(2, 2, 0)
+    AP_CG_CASE(2, 2, 2)
+    AP_CG_CASE(2, 2, 4)
+    AP_CG_CASE(2, 3, 1)
+    AP_CG_CASE(2, 3, 3)
+    AP_CG_CASE(2, 3, 5)
+    AP_CG_CASE(2, 4, 2)
+    AP_CG_CASE(2, 4, 4)
+    AP_CG_CASE(2, 4, 6)
+    AP_CG_CASE(3, 0, 3)
+    AP_CG_CASE(3, 1, 2)
+    AP_CG_CASE(3, 1, 4)
+    AP_CG_CASE(3, 2, 1)
+    AP_CG_CASE(3, 2, 3)
+    AP_CG_CASE(3, 2, 5)
+    AP_CG_CASE(3, 3, 0)
+    AP_CG_CASE(3, 3, 2)
+    AP_CG_CASE(3, 3, 4)
+    AP_CG_CASE(3, 3, 6)
+    AP_CG_CASE(3, 4, 1)
+    AP_CG_CASE(3, 4, 3)
+    AP_CG_CASE(3, 4, 5)
+    AP_CG_CASE(3, 4, 7)
+    AP_CG_CASE(4, 0, 4)
+    AP_CG_CASE(4, 1, 3)
+    AP_CG_CASE(4, 1, 5)
+    AP_CG_CASE(4, 2, 2)
+    AP_CG_CASE(4, 2, 4)
+    AP_CG_CASE(4, 2, 6)
+    AP_CG_CASE(4, 3, 1)
+    AP_CG_CASE(4, 3, 3)
+    AP_CG_CASE(4, 3, 5)
+    AP_CG_CASE(4, 3, 7)
+    AP_CG_CASE(4, 4, 0)
+    AP_CG_CASE(4, 4, 2)
+    AP_CG_CASE(4, 4, 4)
+    AP_CG_CASE(4, 4, 6)
+    AP_CG_CASE(4, 4, 8)
+    default: break;
+  }
+}
+#undef AP_CG_CASE
+
+// Coupling of channel groups: lane = (member j = lane/8, atom t = lane%8).
+// MODE 0: build X (bf16 hi/lo into XT).  MODE 1: adjoint from Z into the
+// gradient om (LDS atomics) and phi partial (returned).
+template <int MODE, int L>
+__device__ __forceinline__ float couple_groups(const MixDev& m, const MixL& P,
+                                               const float* A, __bf16* xh, __bf16* xl,
+                                               const float* Z, float* om, int wave, int lane) {
+  const int w = 2 * L + 1;
+  const int t = lane & 7;
+  const int j = lane >> 3;
+  float phi = 0.f;
+  for (int g = wave; g < P.ngrp; g += kMWaves) {
+    const int gid = P.grp0 + g;
+    const int pat = uni(m.grp_pat[gid]);
+    const int la = uni(m.pat_hdr[5 * pat]), lb = uni(m.pat_hdr[5 * pat + 1]);
+    const int key = uni(m.pat_hdr[5 * pat + 3]), c0 = uni(m.pat_hdr[5 * pat + 4]);
+    const int4 mem = m.grp_mem[gid * 8 + j];
+    if (mem.x < 0) continue;
+    const float* At = A + t * m.apad;
+    float Aa[2 * kMaxL + 1], Ab[2 * kMaxL + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxL + 1; ++q) {
+      Aa[q] = q <= 2 * la ? At[mem.y + q] : 0.f;
+      Ab[q] = q <= 2 * lb ? At[mem.z + q] : 0.f;
+    }
+    float Xv[4 * kMaxL + 1];
+#pragma unroll
+    for (int q = 0; q < 4 * kMaxL + 1; ++q) Xv[q] = 0.f;
+    if (MODE == 0) {
+      couple_dispatch<0, L>(key, m.pat_coef + c0, Aa, Ab, Xv, nullptr, nullptr, nullptr);
+      const int col0 = t * w;
+#pragma unroll
+      for (int M = 0; M < 4 * kMaxL + 1; ++M) {
+        if (M >= w) break;
+        __bf16 hi, lo;
+        split_bf16(Xv[M], hi, lo);
+        xh[(col0 + M) * P.kstr + mem.x] = hi;
+        xl[(col0 + M) * P.kstr + mem.x] = lo;
+      }
+    } else {
+      float Zv[4 * kMaxL + 1];
+      const float* Zr = Z + mem.x * P.zstr + t * w;
+#pragma unroll
+      for (int M = 0; M < 4 * kMaxL + 1; ++M) Zv[M] = M < w ? Zr[M] : 0.f;
+      float ga[2 * kMaxL + 1], gb[2 * kMaxL + 1];
+#pragma unroll
+      for (int q = 0; q < 2 * kMaxL + 1; ++q) { ga[q] = 0.f; gb[q] = 0.f; }
+      couple_dispatch<1, L>(key, m.pat_coef + c0, Aa, Ab, Xv, Zv, ga, gb);
+#pragma unroll
+      for (int M = 0; M < 4 * kMaxL + 1; ++M) phi += Xv[M] * Zv[M];
+      float* omt = om + t * m.apad;
+#pragma unroll
+      for (int q = 0; q < 2 * kMaxL + 1; ++q) {
+        if (q <= 2 * la) atomicAdd(omt + mem.y + q, ga[q]);
+        if (q <= 2 * lb) atomicAdd(omt + mem.z + q, gb[q]);
+      }
+    }
+  }
+  return phi;
+}
+
+template <int L, int RTW, int CTN>
+__device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
+                                       float* om2, unsigned char* big, float* phi_lds, int wave,
+                                       int lane, int tid, float& phi1, float& phi2) {
+  const int w = 2 * L + 1;
+  const int ncols = kMT * w;
+  __bf16* xh = reinterpret_cast<__bf16*>(big);
+  __bf16* xl = xh + (size_t)P.ct * 16 * P.kstr;
+  float* Z = reinterpret_cast<float*>(big);
+  for (int p = 0; p < 2; ++p) {
+    // coupled operand X_L (zero padding, channel rows, A rows, constant row)
+    {
+      uint4* z4 = reinterpret_cast<uint4*>(big);
+      const int n16 = (P.ct * 16 * P.kstr * 2 * 2) / 16;
+      for (int q = tid; q < n16; q += kMThreads) z4[q] = uint4{0u, 0u, 0u, 0u};
+    }
+    __syncthreads();
+    couple_groups<0, L>(m, P, A, xh, xl, nullptr, nullptr, wave, lane);
+    if (P.arow) {
+      for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
+        const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
+        const float v = A[t * m.apad + n * m.nlm + L * L + M];
+        __bf16 hi, lo;
+        split_bf16(v, hi, lo);
+        xh[col * P.kstr + P.nch + n] = hi;
+        xl[col * P.kstr + P.nch + n] = lo;
+      }
+    }
+    if (L == 0 && tid < kMT) {
+      xh[tid * P.kstr + P.nch + m.n_max] = (__bf16)1.0f;
+      xl[tid * P.kstr + P.nch + m.n_max] = (__bf16)0.0f;
+    }
+    __syncthreads();
+    // Z_L of coefficient set p
+    f32x4 acc[RTW][CTN];
+    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, p);
+    __syncthreads();  // X is dead from here on
+    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
+    __syncthreads();
+    float* om = p == 0 ? om1 : om2;
+    const float ph = couple_groups<1, L>(m, P, A, nullptr, nullptr, Z, om, wave, lane);
+    // A rows: phi += A Z, dphi/dA += Z
+    if (P.arow) {
+      for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
+        const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
+        const int ai = t * m.apad + n * m.nlm + L * L + M;
+        const float z = Z[(P.nch + n) * P.zstr + col];
+        atomicAdd(&phi_lds[t * 2 + p], A[ai] * z);
+        atomicAdd(&om[ai], z);
+      }
+    }
+    if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], Z[(P.nch + m.n_max) * P.zstr + tid]);
+    if (p == 0) phi1 += ph; else phi2 += ph;
+    __syncthreads();
+  }
+}
+
+// ---- kernel 1: bond basis and atomic basis A, one wavefront per ACE atom
+constexpr int kBasisWaves = 4;
+
+__global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
+    SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ count, const int32_t* __restrict__ ace_list,
+    const int32_t* __restrict__ n_ace_p, int n_all, float* __restrict__ A_out) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int stride = m.nnl + m.nlm;
+  float* RY = reinterpret_cast<float*>(lds) + wave * 64 * stride;
+  const int n = sv.n_atoms;
+  const int n_items = ace_list ? *n_ace_p : n_all;
+  const int item = blockIdx.x * kBasisWaves + wave;
+  if (item >= n_items) return;  // whole wavefront
+  const int a = ace_list ? ace_list[item] : item;
+  const int c = count[a];
+  const int sy = sv.sys_of[a];
+  const int lp1 = m.l_max + 1;
+  const float rc = (float)m.rc;
+  float acc[(kMaxN * kMaxLM + 63) / 64];
+#pragma unroll
+  for (int q = 0; q < (kMaxN * kMaxLM + 63) / 64; ++q) acc[q] = 0.f;
+  for (int base = 0; base < c; base += 64) {
+    const int s = base + lane;
+    float* o = RY + lane * stride;
+    if (s < c) {
+      const int j = nbr[(int64_t)s * n + a];
+      double dx, dy, dz;
+      displacement(sv.ortho[sy] != 0, sv.H + 9 * sy, sv.Hi + 9 * sy, sv.per, pos[a], pos[n + a],
+                   pos[2 * n + a], pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+      const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+      float g[kMaxK], dg[kMaxK];
+      cheb_basis<float>(m.K, rc, r, g, dg);
+      for (int nl = 0; nl < m.nnl; ++nl) {
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < m.K) v += m.Wf[nl * m.K + k] * g[k];
+        o[nl] = v;
+      }
+      float Y[kMaxLM];
+      const float ir = 1.f / r;
+      real_ylm<float>(m.l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, Y, nullptr);
+#pragma unroll
+      for (int q = 0; q < kMaxLM; ++q)
+        if (q < m.nlm) o[m.nnl + q] = Y[q];
+    } else {
+      for (int q = 0; q < stride; ++q) o[q] = 0.f;
+    }
+    __syncwarp_ap();
+    const int nb = min(64, c - base);
+#pragma unroll
+    for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
+      const int e = lane + 64 * r;
+      if (e >= m.nA) break;
+      const int nn = e / m.nlm, lm = e % m.nlm;
+      int l = 0;
+      while ((l + 1) * (l + 1) <= lm) ++l;
+      float v = 0.f;
+      for (int s2 = 0; s2 < nb; ++s2) v += RY[s2 * stride + nn * lp1 + l] * RY[s2 * stride + m.nnl + lm];
+      acc[r] += v;
+    }
+    __syncwarp_ap();
+  }
+#pragma unroll
+  for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
+    const int e = lane + 64 * r;
+    if (e < m.nA) A_out[(int64_t)item * m.nA + e] = acc[r];
+  }
+}
+
+// ---- kernel 2: coupling, folded contraction, adjoint for tiles of 8 atoms
+__global__ __launch_bounds__(kMThreads, 1) void k_ace_core(
+    MixDev m, const int32_t* __restrict__ n_ace_p, int n_all, const float* __restrict__ A_in,
+    int32_t* __restrict__ counter, float* __restrict__ om_out, float* __restrict__ phi_out) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* A = reinterpret_cast<float*>(lds);
+  float* om1 = A + kMT * m.apad;
+  float* om2 = om1 + kMT * m.apad;
+  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2]
+  unsigned char* big = lds + m.big_off;
+  __shared__ int s_tile;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
+  const int n_items = n_ace_p ? *n_ace_p : n_all;
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile * kMT >= n_items) break;
+    const int nt = min(kMT, n_items - tile * kMT);
+    for (int q = tid; q < 3 * kMT * m.apad + 2 * kMT; q += kMThreads) A[q] = 0.f;
+    __syncthreads();
+    for (int q = tid; q < nt * m.nA; q += kMThreads) {
+      const int t = q / m.nA, e = q % m.nA;
+      A[t * m.apad + e] = A_in[(int64_t)(tile * kMT) * m.nA + q];
+    }
+    __syncthreads();
+    float phi1 = 0.f, phi2 = 0.f;
+    for (int L = 0; L <= m.L_max; ++L) {
+      const MixL P = load_level(m.lv_d + L);
+      switch (L) {
+        case 0: rank_L<0, 4, 1>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 1: rank_L<1, 5, 2>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 2: rank_L<2, 6, 3>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 3: rank_L<3, 6, 4>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 4: rank_L<4, 5, 5>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 5: rank_L<5, 4, 6>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 6: rank_L<6, 3, 7>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        case 7: rank_L<7, 2, 8>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+        default: rank_L<8, 2, 9>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
+      }
+    }
+    // lanes of one atom (lane % 8) hold channel partials of phi
+    atomicAdd(&phi_lds[(lane & 7) * 2 + 0], phi1);
+    atomicAdd(&phi_lds[(lane & 7) * 2 + 1], phi2);
+    __syncthreads();
+    for (int q = tid; q < nt * m.nA; q += kMThreads) {
+      const int t = q / m.nA, e = q % m.nA;
+      const int64_t o = (int64_t)(tile * kMT) * m.nA + q;
+      om_out[2 * o] = om1[t * m.apad + e];
+      om_out[2 * o + 1] = om2[t * m.apad + e];
+    }
+    if (tid < 2 * nt) phi_out[(int64_t)tile * kMT * 2 + tid] = phi_lds[tid];
+    __syncthreads();
+  }
+}
+
+// ---- kernel 3: embedding (FP64), bond gradients and virial, one wavefront per atom
+__global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
+    SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
+    const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
+    const float* __restrict__ om_in, const float* __restrict__ phi_in, float* __restrict__ pair_g,
+    double* __restrict__ e_atom, double* __restrict__ vir) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float* om = reinterpret_cast<float*>(lds) + wave * m.apad;
+  const int n = sv.n_atoms;
+  const int n_items = ace_list ? *n_ace_p : n_all;
+  const int item = blockIdx.x * kBasisWaves + wave;
+  if (item >= n_items) return;  // whole wavefront
+  const int a = ace_list ? ace_list[item] : item;
+  const double lam = lambda ? lambda[a] : 1.0;
+  const double p1 = 0.5 * (double)phi_in[2 * (int64_t)item];
+  const double p2 = 0.5 * (double)phi_in[2 * (int64_t)item + 1];
+  const double root = sqrt(fabs(p2) + 1e-6);
+  const double E = p1 + root;
+  const double sp = (p2 >= 0.0 ? 1.0 : -1.0) / (2.0 * root);
+  for (int e = lane; e < m.nA; e += 64) {
+    const int64_t o = (int64_t)item * m.nA + e;
+    om[e] = (float)(lam * ((double)om_in[2 * o] + sp * (double)om_in[2 * o + 1]));
+  }
+  __syncwarp_ap();
+  const int c = count[a];
+  const int sy = sv.sys_of[a];
+  const int lp1 = m.l_max + 1;
+  const float rc = (float)m.rc;
+  double w9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int s = lane; s < c; s += 64) {
+    const int j = nbr[(int64_t)s * n + a];
+    double dx, dy, dz;
+    displacement(sv.ortho[sy] != 0, sv.H + 9 * sy, sv.Hi + 9 * sy, sv.per, pos[a], pos[n + a],
+                 pos[2 * n + a], pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float ir = 1.f / r;
+    float g[kMaxK], dg[kMaxK];
+    cheb_basis<float>(m.K, rc, r, g, dg);
+    float ca[kMaxLM], cb[kMaxLM];
+#pragma unroll
+    for (int q = 0; q < kMaxLM; ++q) { ca[q] = 0.f; cb[q] = 0.f; }
+    for (int nn = 0; nn < m.n_max; ++nn) {
+#pragma unroll
+      for (int l = 0; l <= kMaxL; ++l) {
+        if (l > m.l_max) break;
+        float R = 0.f, dR = 0.f;
+        const float* Wr = m.Wf + (nn * lp1 + l) * m.K;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < m.K) { R += Wr[k] * g[k]; dR += Wr[k] * dg[k]; }
+        const float* omn = om + nn * m.nlm;
+#pragma unroll
+        for (int q = l * l; q < (l + 1) * (l + 1); ++q) {
+          ca[q] += omn[q] * R;
+          cb[q] += omn[q] * dR;
+        }
+      }
+    }
+    float rad, gx, gy, gz;
+    ylm_contract<float>(m.l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, ca, cb, rad, gx, gy, gz);
+    gx += rad * fx * ir;
+    gy += rad * fy * ir;
+    gz += rad * fz * ir;
+    float* o = pair_g + ((int64_t)item * cap + s) * 3;
+    o[0] = gx; o[1] = gy; o[2] = gz;
+    w9[0] -= dx * gx; w9[1] -= dx * gy; w9[2] -= dx * gz;
+    w9[3] -= dy * gx; w9[4] -= dy * gy; w9[5] -= dy * gz;
+    w9[6] -= dz * gx; w9[7] -= dz * gy; w9[8] -= dz * gz;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w9[k] = wave_sum_f64(w9[k]);
+  if (lane == 0) {
+    if (vir)
+      for (int k = 0; k < 9; ++k) vir[(int64_t)k * n + a] = w9[k];
+    e_atom[a] += lam * E;
+  }
+}
+
+size_t ace_mixed_lds_bytes(const MixDev& m) { return m.big_off + m.big_bytes; }
+
+hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+                            const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
+                            const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
+                            float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
+                            double* e_atom, double* vir_atom, hipStream_t s, int phase) {
+  const MixDev& m = c.mix;
+  // grids are sized for every atom; wavefronts past *n_ace leave at once
+  const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
+  if (phase == 0) {
+    if (n_atoms == 0) return hipSuccess;
+    const size_t lds = (size_t)kBasisWaves * 64 * (m.nnl + m.nlm) * 4;
+    hipLaunchKernelGGL(k_ace_basis, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr,
+                       count, ace_list, n_ace, n_atoms, A_buf);
+  } else if (phase == 1) {
+    int dev = 0, n_cu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t lds = ace_mixed_lds_bytes(m);
+    hipError_t e = hipFuncSetAttribute((const void*)k_ace_core,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ace_core, dim3(n_cu), dim3(kMThreads), lds, s, m,
+                       ace_list ? n_ace : nullptr, n_atoms, A_buf, counter, om_buf, phi_buf);
+  } else {
+    if (n_atoms == 0) return hipSuccess;
+    const size_t lds = (size_t)kBasisWaves * m.apad * 4;
+    hipLaunchKernelGGL(k_ace_grad, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr,
+                       count, cap, lambda, ace_list, n_ace, n_atoms, om_buf, phi_buf, pair_g,
+                       e_atom, vir_atom);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ap
