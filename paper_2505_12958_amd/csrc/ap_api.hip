@@ -496,7 +496,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   x.Wf = a.Wf;
   x.ynorm = a.ynorm;
   double mfma_flops = 0;
-  static const int kRtwMax[2 * kMaxL + 1] = {4, 5, 6, 6, 5, 4, 3, 2, 2};  // = kernel tiling
+  std::vector<int32_t> pat_off(225, -1);
+  static const int kRtwMax[2 * kMaxL + 1] = {3, 3, 3, 3, 3, 2, 2, 1, 1};  // = kernel tiling
   std::vector<int32_t> bt_ptr, bt_kt, bt_idx, grp_pat, pat_hdr;
   std::vector<int4> grp_mem;
   std::vector<CgEnt> pat_ent;
@@ -520,6 +521,40 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     memcpy(&f, &u, 4);
     return f;
   };
+  // coupling coefficients of every valid (la, lb, L), over the selection-rule
+  // superset in (m1, m2, M) order, addressed by key la*45 + lb*9 + L
+  for (int la = 0; la <= lmax; ++la)
+    for (int lb = 0; lb <= lmax; ++lb)
+      for (int L = std::abs(la - lb); L <= std::min(la + lb, Lmax); ++L) {
+        if ((la + lb + L) & 1) continue;
+        auto key = std::make_tuple(la, lb, L);
+        if (!cgcache.count(key)) {
+          std::vector<double> c;
+          if (!real_cg(la, lb, L, c)) return fail(ctx, AP_ERR_ARG, "complex coupling coefficient");
+          cgcache[key] = c;
+        }
+        const auto& C = cgcache[key];
+        const int w1 = 2 * la + 1, w2 = 2 * lb + 1, w = 2 * L + 1;
+        pat_off[la * 45 + lb * 9 + L] = (int32_t)pat_coef.size();
+        for (int p = 0; p < w1; ++p)
+          for (int q = 0; q < w2; ++q)
+            for (int M = 0; M < w; ++M) {
+              const double c = C[((size_t)p * w2 + q) * w + M];
+              if (rule(p - la, q - lb, M - L)) {
+                pat_coef.push_back((float)c);
+              } else if (c != 0.0) {
+                return fail(ctx, AP_ERR_ARG, "coupling coefficient outside the selection rule");
+              }
+            }
+      }
+  // channel rows by unordered pair, for the adjoint gather
+  const int nidx = nmax * lp1;
+  std::vector<int32_t> rowtab((size_t)(Lmax + 1) * nidx * nidx, -1);
+  for (auto& kv : chan) {
+    const int L = std::get<0>(kv.first), xa = std::get<1>(kv.first), xb = std::get<2>(kv.first);
+    rowtab[((size_t)L * nidx + xa) * nidx + xb] = kv.second;
+    rowtab[((size_t)L * nidx + xb) * nidx + xa] = kv.second;
+  }
   for (int L = 0; L <= Lmax; ++L) {
     MixL& P = x.lv[L];
     const int w = 2 * L + 1;
@@ -529,11 +564,13 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     P.arow = a.has_arow[L];
     const int kpad = (P.nrow + 31) / 32 * 32;
     P.kt = kpad / 32;
-    P.kstr = kpad + 8;
+    // column stride of the operand in LDS: 4 dwords mod 32 banks, so the
+    // 16-byte operand reads of 8 consecutive columns hit distinct banks
+    P.kstr = kpad + (kpad % 64 == 0 ? 8 : 40);
     P.ct = (8 * w + 15) / 16;
     P.rt = 2 * P.nrow16 / 16;
     P.zstr = 8 * w + 1;
-    if ((P.nrow16 / 16 + 3) / 4 > kRtwMax[L] || P.ct > L + 1)
+    if ((P.nrow16 / 16 + 7) / 8 > kRtwMax[L] || P.ct > L + 1)
       return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's register tiling");
     big = std::max(big, (size_t)P.ct * 16 * P.kstr * 2 * 2);
     big = std::max(big, (size_t)P.nrow * P.zstr * 4);
@@ -602,28 +639,22 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
               const double c = C[((size_t)p * w2 + q) * w + M];
               if (c != 0.0) pat_ent.push_back(CgEnt{(int8_t)p, (int8_t)q, (int8_t)M, 0, (float)c});
             }
-        // coefficients over the selection-rule superset, (m1, m2, M) order
-        const int c0 = (int)pat_coef.size();
-        for (int p = 0; p < w1; ++p)
-          for (int q = 0; q < w2; ++q)
-            for (int M = 0; M < w; ++M) {
-              const double c = C[((size_t)p * w2 + q) * w + M];
-              if (rule(p - la, q - lb, M - L)) {
-                pat_coef.push_back((float)c);
-              } else if (c != 0.0) {
-                return fail(ctx, AP_ERR_ARG, "coupling coefficient outside the selection rule");
-              }
-            }
         (void)e0;
         pat_id[key] = (int)pat_hdr.size() / 5;
-        pat_hdr.insert(pat_hdr.end(), {la, lb, L, la * 45 + lb * 9 + L, c0});
+        pat_hdr.insert(pat_hdr.end(), {la, lb, L, la * 45 + lb * 9 + L, pat_off[la * 45 + lb * 9 + L]});
       }
       const int pid = pat_id[key];
       const auto& mem = kv.second;
-      for (size_t g = 0; g < mem.size(); g += 8) {
+      // members of a group are taken with stride n_groups from the (a, b)
+      // ordered list, so they rarely share a single index (fewer colliding
+      // atomic adds in the adjoint)
+      const size_t ng = (mem.size() + 7) / 8;
+      for (size_t g = 0; g < ng; ++g) {
         grp_pat.push_back(pid);
-        for (size_t q = g; q < g + 8; ++q)
-          grp_mem.push_back(q < mem.size() ? mem[q] : make_int4(-1, 0, 0, 0));
+        for (size_t q = 0; q < 8; ++q) {
+          const size_t src = g + q * ng;
+          grp_mem.push_back(src < mem.size() ? mem[src] : make_int4(-1, 0, 0, 0));
+        }
       }
     }
     P.ngrp = (int32_t)grp_pat.size() - P.grp0;
@@ -636,7 +667,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       (st = upload_owned(ctx, bt_idx, &x.bt_idx)) || (st = upload_owned(ctx, ctile, &x.ctile)) ||
       (st = upload_owned(ctx, grp_pat, &x.grp_pat)) || (st = upload_owned(ctx, grp_mem, &x.grp_mem)) ||
       (st = upload_owned(ctx, pat_hdr, &x.pat_hdr)) || (st = upload_owned(ctx, pat_ent, &x.pat_ent)) ||
-      (st = upload_owned(ctx, pat_coef, &x.pat_coef)))
+      (st = upload_owned(ctx, pat_coef, &x.pat_coef)) || (st = upload_owned(ctx, pat_off, &x.pat_off)) ||
+      (st = upload_owned(ctx, rowtab, &x.rowtab)))
     return st;
   {
     std::vector<MixL> lv(x.lv, x.lv + Lmax + 1);
@@ -883,7 +915,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if (N > 0 && (!pos || !e_atom || !force)) return fail(ctx, AP_ERR_ARG, "pos/e_atom/force is NULL");
   const size_t gsz = ctx->precision == AP_PREC_FP64 ? 8 : 4;
   if ((st = ensure(ctx, ctx->ace_row, 4 * (size_t)std::max<int64_t>(N, 1))) ||
-      (st = ensure(ctx, ctx->ace_counter, 64)) ||
+      (st = ensure(ctx, ctx->ace_counter, 256)) ||
       (st = ensure(ctx, ctx->pair_g, gsz * 3 * (size_t)nl->capacity * std::max<int64_t>(N, 1))) ||
       (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
     return st;

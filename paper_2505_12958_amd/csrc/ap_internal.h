@@ -113,6 +113,8 @@ struct MixDev {
   const int32_t* pat_hdr;  // 5 ints per pattern: la, lb, L, switch key, first coefficient
   const CgEnt* pat_ent;
   const float* pat_coef;   // coefficients per pattern over the selection-rule superset
+  const int32_t* pat_off;  // first coefficient of pattern key la*45 + lb*9 + L (-1: invalid)
+  const int32_t* rowtab;   // [L][a][p]: row of the coupled channel {a, p} in X_L, or -1
   int32_t big_off, big_bytes;  // LDS layout
 };
 

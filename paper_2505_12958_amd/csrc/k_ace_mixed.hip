@@ -1,6 +1,6 @@
 // ACE part of the AP force, mixed-precision path.
 //
-// One workgroup (256 threads, 4 wavefronts, one per SIMD) evaluates a tile of 8 ACE-active
+// One workgroup (512 threads, 8 wavefronts, two per SIMD) evaluates a tile of 8 ACE-active
 // atoms taken from a global counter (persistent loop), entirely on chip:
 //
 //  1. bond basis in FP32 from the FP64 minimum-image displacement; the
@@ -15,8 +15,9 @@
 //        stored (pre-split into bf16 hi/lo), each product taken as
 //        hi*hi + hi*lo + lo*hi with FP32 accumulation;
 //     c. Z_L of each set goes to LDS (over the dead X_L) and the adjoint
-//        dphi/dA = (dX_L/dA)^T Z_L is gathered per (channel, atom) and added
-//        to the atom's gradient; phi = X.Z/2 is accumulated on the way;
+//        dphi/dA = (dX_L/dA)^T Z_L is formed per (channel, atom) and added
+//        to the atom's gradient; phi itself follows from Euler's theorem
+//        for homogeneous functions (see the end of the tile loop);
 //  3. embedding E = phi1 + sqrt(|phi2| + 1e-6) and its derivative in FP64;
 //  4. per-bond gradients g_ij (FP32) and the atom's virial (FP64 sums).
 #include "ace_basis.h"
@@ -30,7 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMT = 8;
-constexpr int kMThreads = 256;
+constexpr int kMThreads = 512;
 constexpr int kMWaves = kMThreads / 64;
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -39,11 +40,20 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast
 // wavefront-uniform explicitly so they live in scalar registers.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Read-only model tables are read through the constant address space, so
+// wavefront-uniform indices become scalar loads (the kernel never writes them).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) { return (cptr<T>)p; }
+
 __device__ __forceinline__ MixL load_level(const MixL* p) {
-  MixL P = *p;
-  P.nrow = uni(P.nrow); P.nrow16 = uni(P.nrow16); P.nch = uni(P.nch); P.arow = uni(P.arow);
-  P.rt = uni(P.rt); P.ct = uni(P.ct); P.kt = uni(P.kt); P.kstr = uni(P.kstr); P.zstr = uni(P.zstr);
-  P.grp0 = uni(P.grp0); P.ngrp = uni(P.ngrp); P.bt0 = uni(P.bt0);
+  static_assert(sizeof(MixL) == 12 * sizeof(int32_t), "MixL is 12 int32 fields");
+  cptr<int32_t> q = as_const(reinterpret_cast<const int32_t*>(p));
+  MixL P;
+  P.nrow = uni(q[0]); P.nrow16 = uni(q[1]); P.nch = uni(q[2]); P.arow = uni(q[3]);
+  P.rt = uni(q[4]); P.ct = uni(q[5]); P.kt = uni(q[6]); P.kstr = uni(q[7]); P.zstr = uni(q[8]);
+  P.grp0 = uni(q[9]); P.ngrp = uni(q[10]); P.bt0 = uni(q[11]);
   return P;
 }
 
@@ -80,8 +90,8 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
   for (int i = 0; i < RTW; ++i) {
     const int rt = wave + kMWaves * i;
     if (rt < rt_set) {
-      cur[i] = uni(m.bt_ptr[P.bt0 + p * rt_set + rt]);
-      end[i] = uni(m.bt_ptr[P.bt0 + p * rt_set + rt + 1]);
+      cur[i] = uni(as_const(m.bt_ptr)[P.bt0 + p * rt_set + rt]);
+      end[i] = uni(as_const(m.bt_ptr)[P.bt0 + p * rt_set + rt + 1]);
     } else {
       cur[i] = 0;
       end[i] = 0;
@@ -89,36 +99,51 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
   }
   const int col_l = lane & 15;
   const int k_l = 8 * (lane >> 4);
-  for (int kt = 0; kt < P.kt; ++kt) {
-    uint4 ch[RTW], cl[RTW];
-    bool nz[RTW];
-    bool any = false;
+  // coefficient tiles of k tile kt for every owned row tile, one k tile ahead
+  uint4 ch[RTW], cl[RTW], nh[RTW], nl[RTW];
+  bool nz[RTW], nn[RTW];
+  auto fetch = [&](int kt, uint4 (&h)[RTW], uint4 (&l)[RTW], bool (&f)[RTW]) {
 #pragma unroll
     for (int i = 0; i < RTW; ++i) {
-      nz[i] = cur[i] < end[i] && uni(m.bt_kt[cur[i]]) == kt;
-      if (nz[i]) {
-        const int idx = uni(m.bt_idx[cur[i]]);
-        ch[i] = m.ctile[(2 * (size_t)idx) * 64 + lane];
-        cl[i] = m.ctile[(2 * (size_t)idx + 1) * 64 + lane];
+      f[i] = kt < P.kt && cur[i] < end[i] && uni(as_const(m.bt_kt)[cur[i]]) == kt;
+      if (f[i]) {
+        const int idx = uni(as_const(m.bt_idx)[cur[i]]);
+        h[i] = m.ctile[(2 * (size_t)idx) * 64 + lane];
+        l[i] = m.ctile[(2 * (size_t)idx + 1) * 64 + lane];
         ++cur[i];
-        any = true;
       }
     }
-    if (!any) continue;
+  };
+  fetch(0, ch, cl, nz);
+  for (int kt = 0; kt < P.kt; ++kt) {
+    fetch(kt + 1, nh, nl, nn);
+    bool any = false;
 #pragma unroll
-    for (int c = 0; c < CTN; ++c) {
-      if (c >= P.ct) break;
-      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
-      const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
-      const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
+    for (int i = 0; i < RTW; ++i) any = any || nz[i];
+    if (any) {
 #pragma unroll
-      for (int i = 0; i < RTW; ++i) {
-        if (!nz[i]) continue;
-        const bf16x8 ah = as_bf16x8(ch[i]), al = as_bf16x8(cl[i]);
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i][c], 0, 0, 0);
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i][c], 0, 0, 0);
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i][c], 0, 0, 0);
+      for (int c = 0; c < CTN; ++c) {
+        if (c >= P.ct) break;
+        const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
+        const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
+        const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
+        // the three split products, interleaved over independent accumulators
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp) {
+#pragma unroll
+          for (int i = 0; i < RTW; ++i) {
+            if (!nz[i]) continue;
+            const bf16x8 a = as_bf16x8(sp == 2 ? cl[i] : ch[i]);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? bl : bh, acc[i][c], 0, 0, 0);
+          }
+        }
       }
+    }
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      ch[i] = nh[i];
+      cl[i] = nl[i];
+      nz[i] = nn[i];
     }
   }
 }
@@ -160,172 +185,159 @@ __device__ constexpr bool cg_rule(int m1, int m2, int M) {
          (iabs_c(M) == iabs_c(m1) + iabs_c(m2) || iabs_c(M) == iabs_c(iabs_c(m1) - iabs_c(m2)));
 }
 
-// Coupling of one (channel, atom) with compile-time pattern: register
-// indices are static and the coefficients come from uniform loads.
-// MODE 0: X[M] = sum c A_a[m1] A_b[m2].  MODE 1: additionally the adjoint
-// ga[m1] += c A_b[m2] Z[M], gb[m2] += c A_a[m1] Z[M].
-template <int LA, int LB, int L, int MODE>
-__device__ __forceinline__ void couple_static(const float* __restrict__ coef, const float* Aa,
-                                              const float* Ab, float* X, const float* Z, float* ga,
-                                              float* gb) {
+// One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
+// coupling (n, LA) with (n', LB) to rank L.  Register indices are static;
+// the coupling coefficients are scalar loads.
+template <int LA, int LB, int L>
+__device__ __forceinline__ void xbuild_group(cptr<float> coef, const float* At, int4 mem,
+                                             __bf16* xh, __bf16* xl, int kstr, int t) {
+  float Aa[2 * LA + 1], Ab[2 * LB + 1], X[2 * L + 1];
+#pragma unroll
+  for (int q = 0; q <= 2 * LA; ++q) Aa[q] = At[mem.y + q];
+#pragma unroll
+  for (int q = 0; q <= 2 * LB; ++q) Ab[q] = At[mem.z + q];
+#pragma unroll
+  for (int q = 0; q <= 2 * L; ++q) X[q] = 0.f;
   int k = 0;
 #pragma unroll
-  for (int i = 0; i <= 2 * LA; ++i) {
+  for (int i = 0; i <= 2 * LA; ++i)
 #pragma unroll
-    for (int j = 0; j <= 2 * LB; ++j) {
+    for (int jj = 0; jj <= 2 * LB; ++jj)
 #pragma unroll
-      for (int q = 0; q <= 2 * L; ++q) {
-        if (cg_rule(i - LA, j - LB, q - L)) {
-          const float c = coef[k];
+      for (int q = 0; q <= 2 * L; ++q)
+        if (cg_rule(i - LA, jj - LB, q - L)) {
+          X[q] = fmaf(coef[k] * Aa[i], Ab[jj], X[q]);
           ++k;
-          const float ca = c * Aa[i];
-          X[q] = fmaf(ca, Ab[j], X[q]);
-          if (MODE == 1) {
-            const float cz = c * Z[q];
-            ga[i] = fmaf(cz, Ab[j], ga[i]);
-            gb[j] = fmaf(cz, Aa[i], gb[j]);
-          }
         }
-      }
-    }
+  const int col0 = t * (2 * L + 1);
+#pragma unroll
+  for (int q = 0; q <= 2 * L; ++q) {
+    __bf16 hi, lo;
+    split_bf16(X[q], hi, lo);
+    xh[(col0 + q) * kstr + mem.x] = hi;
+    xl[(col0 + q) * kstr + mem.x] = lo;
   }
 }
 
-#define AP_CG_CASE(la, lb, LL)                                              \
-  case (la) * 45 + (lb) * 9 + (LL):                                         \
-    if constexpr (LL == L) couple_static<la, lb, LL, MODE>(coef, Aa, Ab, X, Z, ga, gb); \
+// One adjoint work unit: lane = (target n = lane/8, atom t = lane%8) with
+// target index a = (n, LT); partners (n', LP) for n' in [np0, np1).  Every
+// coupled channel {a, p} of this L is visited from both of its indices (the
+// coupled value is symmetric in them), so the lane owns its sums.
+template <int LT, int LP, int L>
+__device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cptr<float> coef,
+                                             const float* At, const float* Z, float* omt, int j,
+                                             int t, int np0, int np1) {
+  constexpr int w = 2 * L + 1;
+  const int lp1 = m.l_max + 1;
+  const int nidx = m.n_max * lp1;
+  const bool act = j < m.n_max;
+  const int a = j * lp1 + LT;
+  float ga[2 * LT + 1];
+#pragma unroll
+  for (int q = 0; q <= 2 * LT; ++q) ga[q] = 0.f;
+  for (int np = np0; np < np1; ++np) {
+    const int pidx = np * lp1 + LP;
+    const int row = act ? m.rowtab[((size_t)L * nidx + a) * nidx + pidx] : -1;
+    if (__ballot(row >= 0) == 0ull) continue;
+    float Ap[2 * LP + 1], Zv[w];
+#pragma unroll
+    for (int q = 0; q <= 2 * LP; ++q) Ap[q] = At[np * m.nlm + LP * LP + q];
+    const float f = row < 0 ? 0.f : (pidx == a ? 2.f : 1.f);
+    const int zb = (row < 0 ? 0 : row) * P.zstr + t * w;
+#pragma unroll
+    for (int q = 0; q < w; ++q) Zv[q] = f * Z[zb + q];
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i <= 2 * LT; ++i)
+#pragma unroll
+      for (int jj = 0; jj <= 2 * LP; ++jj)
+#pragma unroll
+        for (int q = 0; q < w; ++q)
+          if (cg_rule(i - LT, jj - LP, q - L)) {
+            ga[i] = fmaf(coef[k] * Ap[jj], Zv[q], ga[i]);
+            ++k;
+          }
+  }
+  if (act) {
+#pragma unroll
+    for (int q = 0; q <= 2 * LT; ++q) atomicAdd(omt + q, ga[q]);
+  }
+}
+
+#define AP_XB_CASE(la, lb)                                                           \
+  case (la) * 5 + (lb):                                                              \
+    if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
+      xbuild_group<la, lb, L>(coef, At, mem, xh, xl, kstr, t);                        \
     break;
+#define AP_AD_CASE(la, lb)                                                           \
+  case (la) * 5 + (lb):                                                              \
+    if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
+      adjoint_unit<la, lb, L>(m, P, coef, At, Z, omt, j, t, np0, np1);               \
+    break;
+#define AP_ALL_CASES(X) \
+  X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) \
+  X(2, 0) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) \
+  X(4, 0) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
 
-template <int MODE, int L>
-__device__ __forceinline__ void couple_dispatch(int key, const float* __restrict__ coef,
-                                                const float* Aa, const float* Ab, float* X,
-                                                const float* Z, float* ga, float* gb) {
-  switch (key) {
-    AP_CG_CASE(0, 0, 0)
-    AP_CG_CASE(0, 1, 1)
-    AP_CG_CASE(0, 2, 2)
-    AP_CG_CASE(0, 3, 3)
-    AP_CG_CASE(0, 4, 4)
-    AP_CG_CASE(1, 0, 1)
-    AP_CG_CASE(1, 1, 0)
-    AP_CG_CASE(1, 1, 2)
-    AP_CG_CASE(1, 2, 1)
-    AP_CG_CASE(1, 2, 3)
-    AP_CG_CASE(1, 3, 2)
-    AP_CG_CASE(1, 3, 4)
-    AP_CG_CASE(1, 4, 3)
-    AP_CG_CASE(1, 4, 5)
-    AP_CG_CASE(2, 0, 2)
-    AP_CG_CASE(2, 1, 1)
-    AP_CG_CASE(2, 1, 3)
-    AP_CG_CASE(2, 2, 0)
-    AP_CG_CASE(2, 2, 2)
-    AP_CG_CASE(2, 2, 4)
-    AP_CG_CASE(2, 3, 1)
-    AP_CG_CASE(2, 3, 3)
-    AP_CG_CASE(2, 3, 5)
-    AP_CG_CASE(2, 4, 2)
-    AP_CG_CASE(2, 4, 4)
-    AP_CG_CASE(2, 4, 6)
-    AP_CG_CASE(3, 0, 3)
-    AP_CG_CASE(3, 1, 2)
-    AP_CG_CASE(3, 1, 4)
-    AP_CG_CASE(3, 2, 1)
-    AP_CG_CASE(3, 2, 3)
-    AP_CG_CASE(3, 2, 5)
-    AP_CG_CASE(3, 3, 0)
-    AP_CG_CASE(3, 3, 2)
-    AP_CG_CASE(3, 3, 4)
-    AP_CG_CASE(3, 3, 6)
-    AP_CG_CASE(3, 4, 1)
-    AP_CG_CASE(3, 4, 3)
-    AP_CG_CASE(3, 4, 5)
-    AP_CG_CASE(3, 4, 7)
-    AP_CG_CASE(4, 0, 4)
-    AP_CG_CASE(4, 1, 3)
-    AP_CG_CASE(4, 1, 5)
-    AP_CG_CASE(4, 2, 2)
-    AP_CG_CASE(4, 2, 4)
-    AP_CG_CASE(4, 2, 6)
-    AP_CG_CASE(4, 3, 1)
-    AP_CG_CASE(4, 3, 3)
-    AP_CG_CASE(4, 3, 5)
-    AP_CG_CASE(4, 3, 7)
-    AP_CG_CASE(4, 4, 0)
-    AP_CG_CASE(4, 4, 2)
-    AP_CG_CASE(4, 4, 4)
-    AP_CG_CASE(4, 4, 6)
-    AP_CG_CASE(4, 4, 8)
-    default: break;
-  }
-}
-#undef AP_CG_CASE
-
-// Coupling of channel groups: lane = (member j = lane/8, atom t = lane%8).
-// MODE 0: build X (bf16 hi/lo into XT).  MODE 1: adjoint from Z into the
-// gradient om (LDS atomics) and phi partial (returned).
-template <int MODE, int L>
-__device__ __forceinline__ float couple_groups(const MixDev& m, const MixL& P,
-                                               const float* A, __bf16* xh, __bf16* xl,
-                                               const float* Z, float* om, int wave, int lane) {
-  const int w = 2 * L + 1;
-  const int t = lane & 7;
-  const int j = lane >> 3;
-  float phi = 0.f;
+// Build the channel rows of X_L (bf16 hi/lo) for the 8 atoms of the tile.
+template <int L>
+__device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const float* A, __bf16* xh,
+                                       __bf16* xl, int wave, int lane) {
+  const int t = lane & 7, j = lane >> 3;
+  const float* At = A + t * m.apad;
+  const int kstr = P.kstr;
   for (int g = wave; g < P.ngrp; g += kMWaves) {
     const int gid = P.grp0 + g;
-    const int pat = uni(m.grp_pat[gid]);
-    const int la = uni(m.pat_hdr[5 * pat]), lb = uni(m.pat_hdr[5 * pat + 1]);
-    const int key = uni(m.pat_hdr[5 * pat + 3]), c0 = uni(m.pat_hdr[5 * pat + 4]);
+    const int pat = uni(as_const(m.grp_pat)[gid]);
+    cptr<int32_t> hdr = as_const(m.pat_hdr) + 5 * pat;
+    const int la = uni(hdr[0]), lb = uni(hdr[1]);
+    cptr<float> coef = as_const(m.pat_coef) + uni(as_const(m.pat_off)[la * 45 + lb * 9 + L]);
     const int4 mem = m.grp_mem[gid * 8 + j];
     if (mem.x < 0) continue;
-    const float* At = A + t * m.apad;
-    float Aa[2 * kMaxL + 1], Ab[2 * kMaxL + 1];
-#pragma unroll
-    for (int q = 0; q < 2 * kMaxL + 1; ++q) {
-      Aa[q] = q <= 2 * la ? At[mem.y + q] : 0.f;
-      Ab[q] = q <= 2 * lb ? At[mem.z + q] : 0.f;
-    }
-    float Xv[4 * kMaxL + 1];
-#pragma unroll
-    for (int q = 0; q < 4 * kMaxL + 1; ++q) Xv[q] = 0.f;
-    if (MODE == 0) {
-      couple_dispatch<0, L>(key, m.pat_coef + c0, Aa, Ab, Xv, nullptr, nullptr, nullptr);
-      const int col0 = t * w;
-#pragma unroll
-      for (int M = 0; M < 4 * kMaxL + 1; ++M) {
-        if (M >= w) break;
-        __bf16 hi, lo;
-        split_bf16(Xv[M], hi, lo);
-        xh[(col0 + M) * P.kstr + mem.x] = hi;
-        xl[(col0 + M) * P.kstr + mem.x] = lo;
-      }
-    } else {
-      float Zv[4 * kMaxL + 1];
-      const float* Zr = Z + mem.x * P.zstr + t * w;
-#pragma unroll
-      for (int M = 0; M < 4 * kMaxL + 1; ++M) Zv[M] = M < w ? Zr[M] : 0.f;
-      float ga[2 * kMaxL + 1], gb[2 * kMaxL + 1];
-#pragma unroll
-      for (int q = 0; q < 2 * kMaxL + 1; ++q) { ga[q] = 0.f; gb[q] = 0.f; }
-      couple_dispatch<1, L>(key, m.pat_coef + c0, Aa, Ab, Xv, Zv, ga, gb);
-#pragma unroll
-      for (int M = 0; M < 4 * kMaxL + 1; ++M) phi += Xv[M] * Zv[M];
-      float* omt = om + t * m.apad;
-#pragma unroll
-      for (int q = 0; q < 2 * kMaxL + 1; ++q) {
-        if (q <= 2 * la) atomicAdd(omt + mem.y + q, ga[q]);
-        if (q <= 2 * lb) atomicAdd(omt + mem.z + q, gb[q]);
-      }
+    switch (la * 5 + lb) {
+      AP_ALL_CASES(AP_XB_CASE)
+      default: break;
     }
   }
-  return phi;
 }
+
+// Gradient of phi_p with respect to A from the coupled channels of X_L.
+template <int L>
+__device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
+                                        const float* Z, float* om, int wave, int lane) {
+  const int lp1 = m.l_max + 1;
+  const int j = lane >> 3, t = lane & 7;
+  const float* At = A + t * m.apad;
+  // units (l_target, l_partner, partner range): split partners when few
+  // (l, l') pairs are valid for this L, so every wavefront has work
+  int nvalid = 0;
+  for (int u = 0; u < lp1 * lp1; ++u) {
+    const int lt = u / lp1, lp = u % lp1;
+    if (iabs_c(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0) ++nvalid;
+  }
+  const int nsplit = nvalid >= kMWaves ? 1 : (nvalid * 2 >= kMWaves ? 2 : 4);
+  const int chunk = (m.n_max + nsplit - 1) / nsplit;
+  for (int u = wave; u < lp1 * lp1 * nsplit; u += kMWaves) {
+    const int pr = u / (lp1 * lp1), lt = (u / lp1) % lp1, lp = u % lp1;
+    if (!(iabs_c(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0)) continue;
+    const int np0 = pr * chunk, np1 = min(m.n_max, np0 + chunk);
+    if (np0 >= np1) continue;
+    cptr<float> coef = as_const(m.pat_coef) + uni(as_const(m.pat_off)[lt * 45 + lp * 9 + L]);
+    float* omt = om + t * m.apad + j * m.nlm + lt * lt;
+    switch (lt * 5 + lp) {
+      AP_ALL_CASES(AP_AD_CASE)
+      default: break;
+    }
+  }
+}
+#undef AP_XB_CASE
+#undef AP_AD_CASE
+#undef AP_ALL_CASES
 
 template <int L, int RTW, int CTN>
 __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
                                        float* om2, unsigned char* big, float* phi_lds, int wave,
-                                       int lane, int tid, float& phi1, float& phi2) {
+                                       int lane, int tid) {
   const int w = 2 * L + 1;
   const int ncols = kMT * w;
   __bf16* xh = reinterpret_cast<__bf16*>(big);
@@ -339,7 +351,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       for (int q = tid; q < n16; q += kMThreads) z4[q] = uint4{0u, 0u, 0u, 0u};
     }
     __syncthreads();
-    couple_groups<0, L>(m, P, A, xh, xl, nullptr, nullptr, wave, lane);
+    xbuild<L>(m, P, A, xh, xl, wave, lane);
     if (P.arow) {
       for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
         const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
@@ -362,19 +374,18 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
     store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
     __syncthreads();
     float* om = p == 0 ? om1 : om2;
-    const float ph = couple_groups<1, L>(m, P, A, nullptr, nullptr, Z, om, wave, lane);
+    adjoint<L>(m, P, A, Z, om, wave, lane);
+    if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
     // A rows: phi += A Z, dphi/dA += Z
     if (P.arow) {
       for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
         const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
         const int ai = t * m.apad + n * m.nlm + L * L + M;
         const float z = Z[(P.nch + n) * P.zstr + col];
-        atomicAdd(&phi_lds[t * 2 + p], A[ai] * z);
         atomicAdd(&om[ai], z);
+        atomicAdd(&phi_lds[t * 2 + p], A[ai] * z);
       }
     }
-    if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], Z[(P.nch + m.n_max) * P.zstr + tid]);
-    if (p == 0) phi1 += ph; else phi2 += ph;
     __syncthreads();
   }
 }
@@ -453,10 +464,13 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   }
 }
 
-// ---- kernel 2: coupling, folded contraction, adjoint for tiles of 8 atoms
-__global__ __launch_bounds__(kMThreads, 1) void k_ace_core(
+// ---- kernel 2 (one instance per coupled rank L): coupling, folded
+// contraction and adjoint for tiles of 8 atoms; adds the tile's gradient
+// and phi terms of this L to the per-atom buffers (first rank: writes).
+template <int L, int RTW, int CTN>
+__global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     MixDev m, const int32_t* __restrict__ n_ace_p, int n_all, const float* __restrict__ A_in,
-    int32_t* __restrict__ counter, float* __restrict__ om_out, float* __restrict__ phi_out) {
+    int32_t* __restrict__ counter, float* __restrict__ om_buf, float* __restrict__ phi_buf) {
   extern __shared__ __align__(16) unsigned char lds[];
   float* A = reinterpret_cast<float*>(lds);
   float* om1 = A + kMT * m.apad;
@@ -467,8 +481,9 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_core(
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
   const int n_items = n_ace_p ? *n_ace_p : n_all;
+  const MixL P = load_level(m.lv_d + L);
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(counter, 1);
+    if (tid == 0) s_tile = atomicAdd(counter + L, 1);
     __syncthreads();
     const int tile = s_tile;
     if (tile * kMT >= n_items) break;
@@ -480,32 +495,23 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_core(
       A[t * m.apad + e] = A_in[(int64_t)(tile * kMT) * m.nA + q];
     }
     __syncthreads();
-    float phi1 = 0.f, phi2 = 0.f;
-    for (int L = 0; L <= m.L_max; ++L) {
-      const MixL P = load_level(m.lv_d + L);
-      switch (L) {
-        case 0: rank_L<0, 4, 1>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 1: rank_L<1, 5, 2>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 2: rank_L<2, 6, 3>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 3: rank_L<3, 6, 4>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 4: rank_L<4, 5, 5>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 5: rank_L<5, 4, 6>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 6: rank_L<6, 3, 7>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        case 7: rank_L<7, 2, 8>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-        default: rank_L<8, 2, 9>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid, phi1, phi2); break;
-      }
-    }
-    // lanes of one atom (lane % 8) hold channel partials of phi
-    atomicAdd(&phi_lds[(lane & 7) * 2 + 0], phi1);
-    atomicAdd(&phi_lds[(lane & 7) * 2 + 1], phi2);
+    rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid);
     __syncthreads();
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
       const int t = q / m.nA, e = q % m.nA;
       const int64_t o = (int64_t)(tile * kMT) * m.nA + q;
-      om_out[2 * o] = om1[t * m.apad + e];
-      om_out[2 * o + 1] = om2[t * m.apad + e];
+      float2 v = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
+      if (L > 0) {
+        const float2 old = reinterpret_cast<const float2*>(om_buf)[o];
+        v.x += old.x;
+        v.y += old.y;
+      }
+      reinterpret_cast<float2*>(om_buf)[o] = v;
     }
-    if (tid < 2 * nt) phi_out[(int64_t)tile * kMT * 2 + tid] = phi_lds[tid];
+    if (tid < 2 * nt) {
+      const int64_t o = (int64_t)tile * kMT * 2 + tid;
+      phi_buf[o] = (L > 0 ? phi_buf[o] : 0.f) + phi_lds[tid];
+    }
     __syncthreads();
   }
 }
@@ -515,8 +521,9 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
-    const float* __restrict__ om_in, const float* __restrict__ phi_in, float* __restrict__ pair_g,
-    double* __restrict__ e_atom, double* __restrict__ vir) {
+    const float* __restrict__ A_in, const float* __restrict__ om_in,
+    const float* __restrict__ phi_in, float* __restrict__ pair_g, double* __restrict__ e_atom,
+    double* __restrict__ vir) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -527,8 +534,21 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
   if (item >= n_items) return;  // whole wavefront
   const int a = ace_list ? ace_list[item] : item;
   const double lam = lambda ? lambda[a] : 1.0;
-  const double p1 = 0.5 * (double)phi_in[2 * (int64_t)item];
-  const double p2 = 0.5 * (double)phi_in[2 * (int64_t)item + 1];
+  // phi_p = X.Z/2 summed over L.  X rows are homogeneous in A of degree 2
+  // (coupled channels), 1 (A rows) and 0 (constant row); by Euler's theorem
+  // phi_p = (A . dphi_p/dA + S_A + 2 Z_1)/4 with S_A = A.Z over the A rows and
+  // Z_1 the constant row, accumulated in phi_in.
+  double d1 = 0.0, d2 = 0.0;
+  for (int e = lane; e < m.nA; e += 64) {
+    const int64_t o = (int64_t)item * m.nA + e;
+    const double av = (double)A_in[o];
+    d1 += av * (double)om_in[2 * o];
+    d2 += av * (double)om_in[2 * o + 1];
+  }
+  d1 = wave_sum_f64(d1);
+  d2 = wave_sum_f64(d2);
+  const double p1 = 0.25 * (d1 + (double)phi_in[2 * (int64_t)item]);
+  const double p2 = 0.25 * (d2 + (double)phi_in[2 * (int64_t)item + 1]);
   const double root = sqrt(fabs(p2) + 1e-6);
   const double E = p1 + root;
   const double sp = (p2 >= 0.0 ? 1.0 : -1.0) / (2.0 * root);
@@ -611,17 +631,35 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     int dev = 0, n_cu = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    const size_t lds = ace_mixed_lds_bytes(m);
-    hipError_t e = hipFuncSetAttribute((const void*)k_ace_core,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = launch_fill_i32(counter, 0, 2 * kMaxL + 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ace_core, dim3(n_cu), dim3(kMThreads), lds, s, m,
-                       ace_list ? n_ace : nullptr, n_atoms, A_buf, counter, om_buf, phi_buf);
+    const size_t lds = ace_mixed_lds_bytes(m);
+    const int32_t* na = ace_list ? n_ace : nullptr;
+    for (int L = 0; L <= m.L_max; ++L) {
+      const void* fn = nullptr;
+      switch (L) {
+        case 0: fn = (const void*)k_ace_rank<0, 3, 1>; break;
+        case 1: fn = (const void*)k_ace_rank<1, 3, 2>; break;
+        case 2: fn = (const void*)k_ace_rank<2, 3, 3>; break;
+        case 3: fn = (const void*)k_ace_rank<3, 3, 4>; break;
+        case 4: fn = (const void*)k_ace_rank<4, 3, 5>; break;
+        case 5: fn = (const void*)k_ace_rank<5, 2, 6>; break;
+        case 6: fn = (const void*)k_ace_rank<6, 2, 7>; break;
+        case 7: fn = (const void*)k_ace_rank<7, 1, 8>; break;
+        default: fn = (const void*)k_ace_rank<8, 1, 9>; break;
+      }
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&counter,
+                      (void*)&om_buf, (void*)&phi_buf};
+      e = hipLaunchKernel(fn, dim3(n_cu), dim3(kMThreads), args, lds, s);
+      if (e != hipSuccess) return e;
+    }
   } else {
     if (n_atoms == 0) return hipSuccess;
     const size_t lds = (size_t)kBasisWaves * m.apad * 4;
     hipLaunchKernelGGL(k_ace_grad, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr,
-                       count, cap, lambda, ace_list, n_ace, n_atoms, om_buf, phi_buf, pair_g,
+                       count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf, pair_g,
                        e_atom, vir_atom);
   }
   return hipGetLastError();
