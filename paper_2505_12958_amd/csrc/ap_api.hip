@@ -659,7 +659,10 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     }
     P.ngrp = (int32_t)grp_pat.size() - P.grp0;
   }
-  x.big_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16) * 4 + 15) / 16 * 16);
+  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16) * 4 + 15) / 16 * 16);
+  size_t tab = (size_t)nidx * nidx * 4;
+  for (int L = 0; L <= Lmax; ++L) tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16);
+  x.big_off = (int32_t)((x.tab_off + tab + 15) / 16 * 16);
   x.big_bytes = (int32_t)big;
   if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
     return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");

@@ -115,6 +115,7 @@ struct MixDev {
   const float* pat_coef;   // coefficients per pattern over the selection-rule superset
   const int32_t* pat_off;  // first coefficient of pattern key la*45 + lb*9 + L (-1: invalid)
   const int32_t* rowtab;   // [L][a][p]: row of the coupled channel {a, p} in X_L, or -1
+  int32_t tab_off;             // LDS: staged channel tables of one L (rows, groups)
   int32_t big_off, big_bytes;  // LDS layout
 };
 

@@ -25,6 +25,8 @@
 #include "geom.h"
 #include "scan.h"
 
+#include <utility>
+
 namespace ap {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -185,6 +187,105 @@ __device__ constexpr bool cg_rule(int m1, int m2, int M) {
          (iabs_c(M) == iabs_c(m1) + iabs_c(m2) || iabs_c(M) == iabs_c(iabs_c(m1) - iabs_c(m2)));
 }
 
+// ---- coupling coefficients as compile-time constants
+// Complex <j1 m1 j2 m2 | J M> from Racah's closed form and the change of
+// basis to the real harmonics (real Y_m = sum_mu U_{m mu} Y^mu with
+// U_{0,0} = 1; m > 0: U_{m,m} = (-1)^m/sqrt2, U_{m,-m} = 1/sqrt2; m < 0, k = |m|:
+// U_{m,k} = -i(-1)^k/sqrt2, U_{m,-k} = i/sqrt2), evaluated by the compiler.
+constexpr double ce_fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+constexpr double ce_sqrt(double x) {
+  if (x <= 0.0) return 0.0;
+  double r = x > 1.0 ? x : 1.0;
+  for (int i = 0; i < 200; ++i) {
+    const double n = 0.5 * (r + x / r);
+    if (n == r) break;
+    r = n;
+  }
+  return r;
+}
+constexpr double ce_cg(int j1, int m1, int j2, int m2, int J, int M) {
+  if (m1 + m2 != M || iabs_c(m1) > j1 || iabs_c(m2) > j2 || iabs_c(M) > J) return 0.0;
+  if (J < iabs_c(j1 - j2) || J > j1 + j2) return 0.0;
+  const double pre = (2 * J + 1) * ce_fact(J + j1 - j2) * ce_fact(J - j1 + j2) * ce_fact(j1 + j2 - J) /
+                     ce_fact(j1 + j2 + J + 1) * ce_fact(J + M) * ce_fact(J - M) * ce_fact(j1 - m1) *
+                     ce_fact(j1 + m1) * ce_fact(j2 - m2) * ce_fact(j2 + m2);
+  double sum = 0.0;
+  for (int k = 0; k <= j1 + j2 - J; ++k) {
+    const int a0 = k, a1 = j1 + j2 - J - k, a2 = j1 - m1 - k, a3 = j2 + m2 - k, a4 = J - j2 + m1 + k,
+              a5 = J - j1 - m2 + k;
+    if (a0 < 0 || a1 < 0 || a2 < 0 || a3 < 0 || a4 < 0 || a5 < 0) continue;
+    const double den = ce_fact(a0) * ce_fact(a1) * ce_fact(a2) * ce_fact(a3) * ce_fact(a4) * ce_fact(a5);
+    sum += ((k & 1) ? -1.0 : 1.0) / den;
+  }
+  return ce_sqrt(pre) * sum;
+}
+// U_{m, mu} as (re, im); zero unless mu = +-m
+struct ce_c2 { double re, im; };
+constexpr ce_c2 ce_u(int m, int mu) {
+  const double s = 0.70710678118654752440;
+  if (m == 0) return mu == 0 ? ce_c2{1.0, 0.0} : ce_c2{0.0, 0.0};
+  if (m > 0) {
+    if (mu == m) return ce_c2{(m & 1) ? -s : s, 0.0};
+    if (mu == -m) return ce_c2{s, 0.0};
+    return ce_c2{0.0, 0.0};
+  }
+  const int k = -m;
+  if (mu == k) return ce_c2{0.0, (k & 1) ? s : -s};
+  if (mu == -k) return ce_c2{0.0, s};
+  return ce_c2{0.0, 0.0};
+}
+constexpr ce_c2 ce_mul(ce_c2 a, ce_c2 b) { return ce_c2{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+constexpr ce_c2 ce_conj(ce_c2 a) { return ce_c2{a.re, -a.im}; }
+// real coupling coefficient C^{l1 l2 L}_{m1 m2 M}
+constexpr double ce_real_cg(int l1, int l2, int L, int m1, int m2, int M) {
+  double acc = 0.0;
+  const int mu1s[2] = {iabs_c(m1), -iabs_c(m1)};
+  const int mu2s[2] = {iabs_c(m2), -iabs_c(m2)};
+  for (int a = 0; a < (m1 == 0 ? 1 : 2); ++a)
+    for (int b = 0; b < (m2 == 0 ? 1 : 2); ++b) {
+      const int mu1 = mu1s[a], mu2 = mu2s[b], mu = mu1 + mu2;
+      if (iabs_c(mu) > L) continue;
+      const ce_c2 u = ce_mul(ce_mul(ce_u(M, mu), ce_conj(ce_u(m1, mu1))), ce_conj(ce_u(m2, mu2)));
+      acc += u.re * ce_cg(l1, mu1, l2, mu2, L, mu);
+    }
+  return acc;
+}
+
+// one entry of the coupling of (LA, m1 index I1) with (LB, m2 index I2) to
+// (L, M index Q), flat index E = (I1 * (2LB+1) + I2) * (2L+1) + Q
+template <int LA, int LB, int L, int E>
+__device__ __forceinline__ void xb_entry(const float* Aa, const float* Ab, float* X) {
+  constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LB + 1),
+                i1 = E / ((2 * L + 1) * (2 * LB + 1));
+  if constexpr (cg_rule(i1 - LA, i2 - LB, q - L)) {
+    constexpr float c = (float)ce_real_cg(LA, LB, L, i1 - LA, i2 - LB, q - L);
+    if constexpr (c != 0.0f) X[q] = fmaf(c * Aa[i1], Ab[i2], X[q]);
+  }
+}
+template <int LT, int LP, int L, int E>
+__device__ __forceinline__ void ad_entry(const float* Ap, const float* Zv, float* ga) {
+  constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LP + 1),
+                i1 = E / ((2 * L + 1) * (2 * LP + 1));
+  if constexpr (cg_rule(i1 - LT, i2 - LP, q - L)) {
+    constexpr float c = (float)ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L);
+    if constexpr (c != 0.0f) ga[i1] = fmaf(c * Ap[i2], Zv[q], ga[i1]);
+  }
+}
+template <int LA, int LB, int L, int... E>
+__device__ __forceinline__ void xb_all(std::integer_sequence<int, E...>, const float* Aa,
+                                       const float* Ab, float* X) {
+  (xb_entry<LA, LB, L, E>(Aa, Ab, X), ...);
+}
+template <int LT, int LP, int L, int... E>
+__device__ __forceinline__ void ad_all(std::integer_sequence<int, E...>, const float* Ap,
+                                       const float* Zv, float* ga) {
+  (ad_entry<LT, LP, L, E>(Ap, Zv, ga), ...);
+}
+
 // One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
 // coupling (n, LA) with (n', LB) to rank L.  Register indices are static;
 // the coupling coefficients are scalar loads.
@@ -198,17 +299,8 @@ __device__ __forceinline__ void xbuild_group(cptr<float> coef, const float* At, 
   for (int q = 0; q <= 2 * LB; ++q) Ab[q] = At[mem.z + q];
 #pragma unroll
   for (int q = 0; q <= 2 * L; ++q) X[q] = 0.f;
-  int k = 0;
-#pragma unroll
-  for (int i = 0; i <= 2 * LA; ++i)
-#pragma unroll
-    for (int jj = 0; jj <= 2 * LB; ++jj)
-#pragma unroll
-      for (int q = 0; q <= 2 * L; ++q)
-        if (cg_rule(i - LA, jj - LB, q - L)) {
-          X[q] = fmaf(coef[k] * Aa[i], Ab[jj], X[q]);
-          ++k;
-        }
+  xb_all<LA, LB, L>(std::make_integer_sequence<int, (2 * LA + 1) * (2 * LB + 1) * (2 * L + 1)>{}, Aa,
+                    Ab, X);
   const int col0 = t * (2 * L + 1);
 #pragma unroll
   for (int q = 0; q <= 2 * L; ++q) {
@@ -225,8 +317,9 @@ __device__ __forceinline__ void xbuild_group(cptr<float> coef, const float* At, 
 // coupled value is symmetric in them), so the lane owns its sums.
 template <int LT, int LP, int L>
 __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cptr<float> coef,
-                                             const float* At, const float* Z, float* omt, int j,
-                                             int t, int np0, int np1) {
+                                             const float* At, const float* Z, float* omt,
+                                             const int32_t* rows_lds, int j, int t, int np0,
+                                             int np1) {
   constexpr int w = 2 * L + 1;
   const int lp1 = m.l_max + 1;
   const int nidx = m.n_max * lp1;
@@ -237,7 +330,7 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
   for (int q = 0; q <= 2 * LT; ++q) ga[q] = 0.f;
   for (int np = np0; np < np1; ++np) {
     const int pidx = np * lp1 + LP;
-    const int row = act ? m.rowtab[((size_t)L * nidx + a) * nidx + pidx] : -1;
+    const int row = act ? rows_lds[a * nidx + pidx] : -1;
     if (__ballot(row >= 0) == 0ull) continue;
     float Ap[2 * LP + 1], Zv[w];
 #pragma unroll
@@ -246,17 +339,8 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
     const int zb = (row < 0 ? 0 : row) * P.zstr + t * w;
 #pragma unroll
     for (int q = 0; q < w; ++q) Zv[q] = f * Z[zb + q];
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i <= 2 * LT; ++i)
-#pragma unroll
-      for (int jj = 0; jj <= 2 * LP; ++jj)
-#pragma unroll
-        for (int q = 0; q < w; ++q)
-          if (cg_rule(i - LT, jj - LP, q - L)) {
-            ga[i] = fmaf(coef[k] * Ap[jj], Zv[q], ga[i]);
-            ++k;
-          }
+    ad_all<LT, LP, L>(std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{},
+                      Ap, Zv, ga);
   }
   if (act) {
 #pragma unroll
@@ -272,7 +356,7 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
 #define AP_AD_CASE(la, lb)                                                           \
   case (la) * 5 + (lb):                                                              \
     if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
-      adjoint_unit<la, lb, L>(m, P, coef, At, Z, omt, j, t, np0, np1);               \
+      adjoint_unit<la, lb, L>(m, P, coef, At, Z, omt, rows_lds, j, t, np0, np1);     \
     break;
 #define AP_ALL_CASES(X) \
   X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) \
@@ -282,7 +366,7 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
 // Build the channel rows of X_L (bf16 hi/lo) for the 8 atoms of the tile.
 template <int L>
 __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const float* A, __bf16* xh,
-                                       __bf16* xl, int wave, int lane) {
+                                       __bf16* xl, const int4* mem_lds, int wave, int lane) {
   const int t = lane & 7, j = lane >> 3;
   const float* At = A + t * m.apad;
   const int kstr = P.kstr;
@@ -292,7 +376,7 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
     cptr<int32_t> hdr = as_const(m.pat_hdr) + 5 * pat;
     const int la = uni(hdr[0]), lb = uni(hdr[1]);
     cptr<float> coef = as_const(m.pat_coef) + uni(as_const(m.pat_off)[la * 45 + lb * 9 + L]);
-    const int4 mem = m.grp_mem[gid * 8 + j];
+    const int4 mem = mem_lds[g * 8 + j];
     if (mem.x < 0) continue;
     switch (la * 5 + lb) {
       AP_ALL_CASES(AP_XB_CASE)
@@ -304,7 +388,8 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
 // Gradient of phi_p with respect to A from the coupled channels of X_L.
 template <int L>
 __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
-                                        const float* Z, float* om, int wave, int lane) {
+                                        const float* Z, float* om, const int32_t* rows_lds,
+                                        int wave, int lane) {
   const int lp1 = m.l_max + 1;
   const int j = lane >> 3, t = lane & 7;
   const float* At = A + t * m.apad;
@@ -336,7 +421,8 @@ __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const fl
 
 template <int L, int RTW, int CTN>
 __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
-                                       float* om2, unsigned char* big, float* phi_lds, int wave,
+                                       float* om2, unsigned char* big, float* phi_lds,
+                                       const int32_t* rows_lds, const int4* mem_lds, int wave,
                                        int lane, int tid) {
   const int w = 2 * L + 1;
   const int ncols = kMT * w;
@@ -351,7 +437,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       for (int q = tid; q < n16; q += kMThreads) z4[q] = uint4{0u, 0u, 0u, 0u};
     }
     __syncthreads();
-    xbuild<L>(m, P, A, xh, xl, wave, lane);
+    xbuild<L>(m, P, A, xh, xl, mem_lds, wave, lane);
     if (P.arow) {
       for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
         const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
@@ -374,7 +460,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
     store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
     __syncthreads();
     float* om = p == 0 ? om1 : om2;
-    adjoint<L>(m, P, A, Z, om, wave, lane);
+    adjoint<L>(m, P, A, Z, om, rows_lds, wave, lane);
     if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
     // A rows: phi += A Z, dphi/dA += Z
     if (P.arow) {
@@ -482,6 +568,12 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
   const int n_items = n_ace_p ? *n_ace_p : n_all;
   const MixL P = load_level(m.lv_d + L);
+  // stage this rank's channel tables in LDS (read by every tile)
+  const int nidx = m.n_max * (m.l_max + 1);
+  int32_t* rows_lds = reinterpret_cast<int32_t*>(lds + m.tab_off);
+  int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
+  for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
+  for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
   for (;;) {
     if (tid == 0) s_tile = atomicAdd(counter + L, 1);
     __syncthreads();
@@ -495,7 +587,7 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
       A[t * m.apad + e] = A_in[(int64_t)(tile * kMT) * m.nA + q];
     }
     __syncthreads();
-    rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, wave, lane, tid);
+    rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
     __syncthreads();
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
       const int t = q / m.nA, e = q % m.nA;
