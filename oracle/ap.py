@@ -102,15 +102,17 @@ class APOracle:
             out["load"] = load
         return out
 
-    def forces_at(self, sysm: Systems, lam, atoms):
-        """Forces on selected atoms only, from brute-force neighbour lists of
-        those atoms and of their neighbours (for full-size sampled checks)."""
+    def forces_at(self, sysm: Systems, lam, atoms, finder=None):
+        """Forces on selected atoms only, from the neighbour lists of those
+        atoms and of their neighbours (for full-size sampled checks); finder
+        defaults to the brute-force Systems.neighbours_of."""
         lam = np.asarray(lam, dtype=np.float64)
         nld = {}
+        finder = sysm.neighbours_of if finder is None else finder
 
         def get(i):
             if i not in nld:
-                nld[i] = sysm.neighbours_of(i)
+                nld[i] = finder(i)
             return nld[i]
 
         need = set()

@@ -145,6 +145,49 @@ class Systems:
                 out[i] = (js[keep], d[keep])
         return out
 
+    def neighbour_finder(self):
+        """Callable i -> (j ascending, d) equal to neighbours_of(i): k-d tree
+        candidates within the cutoff (plus a margin) on large orthorhombic
+        systems, the canonical inclusion rule on every candidate."""
+        from scipy.spatial import cKDTree
+
+        trees = {}
+
+        def tree_of(s):
+            if s not in trees:
+                lo, hi = int(self.sys_offset[s]), int(self.sys_offset[s + 1])
+                H = self.box[s]
+                if not is_orthorhombic(H) or hi - lo < 4000:
+                    trees[s] = None
+                else:
+                    p = self.pos[lo:hi].copy()
+                    shift = np.zeros(3)
+                    size = np.array([H[k][k] if self.periodic[k] else 0.0 for k in range(3)])
+                    for k in range(3):
+                        if not self.periodic[k]:
+                            shift[k] = p[:, k].min()
+                            size[k] = p[:, k].max() - shift[k] + 10.0 * self.cutoff
+                    q = np.mod(p - shift, size)
+                    q = np.where(q >= size, 0.0, q)
+                    trees[s] = (cKDTree(q, boxsize=size), shift, size, lo)
+            return trees[s]
+
+        def find(i):
+            s = self.sys_of[i]
+            t = tree_of(s)
+            if t is None:
+                return self.neighbours_of(i)
+            tree, shift, size, lo = t
+            q = np.mod(self.pos[i] - shift, size)
+            q = np.where(q >= size, 0.0, q)
+            c = tree.query_ball_point(q, self.cutoff * (1 + 1e-6) + 1e-6)
+            js = lo + np.sort(np.asarray(c, dtype=np.int64))
+            d = self.disp(i, js)
+            keep = (r2_of(d) < self.rc2) & (js != i)
+            return js[keep], d[keep]
+
+        return find
+
     def unique_image_check(self, i):
         """Exactly one periodic image of each neighbour lies within rc."""
         s = self.sys_of[i]

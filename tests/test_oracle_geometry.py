@@ -86,3 +86,19 @@ def test_orthorhombic_wrap_rule():
     H = np.diag([10.0, 10.0, 30.0])
     d = displacement(np.array([[0.5, 9.5, 1.0]]), np.array([[9.6, 0.2, 25.0]]), H, (True, True, False))
     assert np.allclose(d, [[-0.9, 0.7, 24.0]])
+
+
+def test_neighbour_finder_matches_brute_force():
+    """The k-d-tree candidate finder returns exactly the brute-force lists
+    (same atoms, same displacements) on a slab above its size threshold."""
+    from paper_2505_12958_amd import workloads as w
+
+    wl = w.workload(3, scale=13)
+    S = Systems.from_workload(wl)
+    find = S.neighbour_finder()
+    rng = np.random.default_rng(5)
+    top = np.argsort(wl.pos[:, 2])[-20:]
+    for i in list(rng.choice(wl.n_atoms, 60, replace=False)) + list(top):
+        a, da = S.neighbours_of(int(i))
+        b, db = find(int(i))
+        assert np.array_equal(a, b) and np.array_equal(da, db)
