@@ -497,8 +497,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   x.ynorm = a.ynorm;
   double mfma_flops = 0;
   std::vector<int32_t> pat_off(225, -1);
-  static const int kRtwMax[2 * kMaxL + 1] = {3, 3, 3, 3, 3, 2, 2, 1, 1};  // = kernel tiling
-  std::vector<int32_t> bt_ptr, bt_kt, bt_idx, grp_pat, pat_hdr;
+
+  std::vector<int32_t> grp_pat, pat_hdr;
   std::vector<int4> grp_mem;
   std::vector<CgEnt> pat_ent;
   std::vector<float> pat_coef;
@@ -570,8 +570,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     P.ct = (8 * w + 15) / 16;
     P.rt = 2 * P.nrow16 / 16;
     P.zstr = 8 * w + 1;
-    if ((P.nrow16 / 16 + 7) / 8 > kRtwMax[L] || P.ct > L + 1)
-      return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's register tiling");
+    if ((P.nrow16 / 16 + kMixWaves - 1) / kMixWaves > kMixRtw[L] || P.ct > L + 1 || nmax > 8)
+      return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model outside the mixed kernels' tiling (n_max <= 8, rows per rank)");
     big = std::max(big, (size_t)P.ct * 16 * P.kstr * 2 * 2);
     big = std::max(big, (size_t)P.nrow * P.zstr * 4);
     // dense folded matrix of this L (both sets)
@@ -580,9 +580,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       D[((size_t)kv.first.first * P.nrow + kv.first.second) * 2] = kv.second.first;
       D[((size_t)kv.first.first * P.nrow + kv.first.second) * 2 + 1] = kv.second.second;
     }
-    P.bt0 = (int32_t)bt_ptr.size();
+    P.bt0 = (int32_t)(ctile.size() / 128);
     for (int rt = 0; rt < P.rt; ++rt) {
-      bt_ptr.push_back((int32_t)bt_kt.size());
       for (int kt = 0; kt < P.kt; ++kt) {
         double v[16][32];
         bool any = false;
@@ -595,11 +594,9 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
             v[i][kk] = val;
             any = any || val != 0.0;
           }
-        if (!any) continue;
+        (void)any;  // all tiles are stored (the folded matrices are almost dense)
         mfma_flops += 3.0 * 2.0 * 16 * 16 * 32 * P.ct / 8.0;  // per atom (tile of 8 atoms)
         const int idx = (int)(ctile.size() / 128);
-        bt_kt.push_back(kt);
-        bt_idx.push_back(idx);
         ctile.resize(ctile.size() + 128);
         for (int lane = 0; lane < 64; ++lane) {
           uint16_t hi[8], lo[8];
@@ -616,14 +613,13 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
         }
       }
     }
-    bt_ptr.push_back((int32_t)bt_kt.size());
     // channel groups of equal (la, lb)
     std::map<std::pair<int, int>, std::vector<int4>> by_pat;
     for (auto& kv : chan) {
       if (std::get<0>(kv.first) != L) continue;
       const int xa = std::get<1>(kv.first), xb = std::get<2>(kv.first);
       const int na = xa / lp1, la = xa % lp1, nb = xb / lp1, lb = xb % lp1;
-      by_pat[{la, lb}].push_back(make_int4(kv.second, na * nlm + la * la, nb * nlm + lb * lb, 0));
+      by_pat[{la, lb}].push_back(make_int4(kv.second, na * nlm + la * la, nb * nlm + lb * lb, la * 5 + lb));
     }
     P.grp0 = (int32_t)grp_pat.size();
     for (auto& kv : by_pat) {
@@ -653,11 +649,65 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
         grp_pat.push_back(pid);
         for (size_t q = 0; q < 8; ++q) {
           const size_t src = g + q * ng;
-          grp_mem.push_back(src < mem.size() ? mem[src] : make_int4(-1, 0, 0, 0));
+          grp_mem.push_back(src < mem.size() ? mem[src] : make_int4(-1, 0, 0, la * 5 + lb));
         }
       }
     }
     P.ngrp = (int32_t)grp_pat.size() - P.grp0;
+  }
+  // adjoint work units per L: (target l, partner l, range of partner n),
+  // cost-balanced over the workgroup's wavefronts (largest first onto the
+  // least-loaded wavefront); cost per partner ~ 2 nnz(CG) + 24
+  std::vector<int32_t> adj_ptr;
+  std::vector<int4> adj_units;
+  for (int L = 0; L <= Lmax; ++L) {
+    struct Unit { int key, np0, np1, lt; double cost; };
+    std::vector<Unit> pats;
+    double total = 0;
+    for (int lt = 0; lt <= lmax; ++lt)
+      for (int lp = 0; lp <= lmax; ++lp) {
+        if (!(std::abs(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0)) continue;
+        bool any = false;
+        for (int na = 0; na < nmax && !any; ++na)
+          for (int nb = 0; nb < nmax && !any; ++nb)
+            any = rowtab[((size_t)L * nidx + na * lp1 + lt) * nidx + nb * lp1 + lp] >= 0;
+        // (L, 0) always has a unit: it also carries the A rows of X_L
+        if (!any && !(lt == L && lp == 0 && L <= lmax)) continue;
+        const auto& C = cgcache[std::make_tuple(lt, lp, L)];
+        int nnz = 0;
+        for (double c : C) nnz += c != 0.0;
+        const double c1 = 2.0 * nnz + 24.0;
+        pats.push_back(Unit{lt * 5 + lp, 0, nmax, lt, c1 * nmax});
+        total += c1 * nmax;
+      }
+    (void)total;
+    // few units (every unit ends with one LDS atomic add per output): split the
+    // costliest partner range in two until there are as many units as wavefronts
+    std::vector<Unit> units = pats;
+    while ((int)units.size() < kMixWaves) {
+      int best = -1;
+      for (int k = 0; k < (int)units.size(); ++k)
+        if (units[k].np1 - units[k].np0 > 1 && (best < 0 || units[k].cost > units[best].cost)) best = k;
+      if (best < 0) break;
+      Unit u = units[best];
+      const int mid = (u.np0 + u.np1) / 2;
+      const double per = u.cost / (u.np1 - u.np0);
+      units[best] = Unit{u.key, u.np0, mid, u.lt, per * (mid - u.np0)};
+      units.push_back(Unit{u.key, mid, u.np1, u.lt, per * (u.np1 - mid)});
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    std::vector<std::vector<Unit>> per(kMixWaves);
+    std::vector<double> load(kMixWaves, 0.0);
+    for (auto& u : units) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      per[w].push_back(u);
+      load[w] += u.cost;
+    }
+    for (int w = 0; w < kMixWaves; ++w) {
+      adj_ptr.push_back((int32_t)adj_units.size());
+      for (auto& u : per[w]) adj_units.push_back(make_int4(u.key, u.np0, u.np1, u.lt));
+    }
+    adj_ptr.push_back((int32_t)adj_units.size());
   }
   x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16) * 4 + 15) / 16 * 16);
   size_t tab = (size_t)nidx * nidx * 4;
@@ -666,18 +716,18 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   x.big_bytes = (int32_t)big;
   if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
     return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");
-  if ((st = upload_owned(ctx, bt_ptr, &x.bt_ptr)) || (st = upload_owned(ctx, bt_kt, &x.bt_kt)) ||
-      (st = upload_owned(ctx, bt_idx, &x.bt_idx)) || (st = upload_owned(ctx, ctile, &x.ctile)) ||
+  if ((st = upload_owned(ctx, ctile, &x.ctile)) ||
       (st = upload_owned(ctx, grp_pat, &x.grp_pat)) || (st = upload_owned(ctx, grp_mem, &x.grp_mem)) ||
       (st = upload_owned(ctx, pat_hdr, &x.pat_hdr)) || (st = upload_owned(ctx, pat_ent, &x.pat_ent)) ||
       (st = upload_owned(ctx, pat_coef, &x.pat_coef)) || (st = upload_owned(ctx, pat_off, &x.pat_off)) ||
-      (st = upload_owned(ctx, rowtab, &x.rowtab)))
+      (st = upload_owned(ctx, rowtab, &x.rowtab)) || (st = upload_owned(ctx, adj_ptr, &x.adj_ptr)) ||
+      (st = upload_owned(ctx, adj_units, &x.adj_units)))
     return st;
   {
     std::vector<MixL> lv(x.lv, x.lv + Lmax + 1);
     if ((st = upload_owned(ctx, lv, &x.lv_d))) return st;
   }
-  ctx->mix_tiles = (double)bt_kt.size();
+  ctx->mix_tiles = (double)(ctile.size() / 128);
   ctx->mix_mfma_flops = mfma_flops;
   return AP_OK;
 }

@@ -82,19 +82,25 @@ struct AceDev {
   int32_t max_xsize;        // max_L nrow*(2L+1)
 };
 
-// ---- mixed-precision ACE model: per-L tiling, block-sparse bf16 tiles,
+// ---- mixed-precision ACE model: per-L tiling, dense split-bf16 tiles,
 // channel groups of equal (l_a, l_b) with their coupling entries
 struct CgEnt {
   int8_t m1, m2, M, pad;
   float c;
 };
 
+// Work-group shape of the mixed rank kernels: kMixWaves wavefronts; each
+// owns at most kMixRtw[L] 16-row tiles of one coefficient set of C_L
+// (row tile rt = wave + kMixWaves * i).
+constexpr int kMixWaves = 12;
+constexpr int kMixRtw[2 * kMaxL + 1] = {1, 2, 2, 2, 2, 1, 1, 1, 1};
+
 struct MixL {
   int32_t nrow, nrow16, nch, arow;  // rows of X_L, padded to 16, channel rows, has A rows
   int32_t rt, ct, kt;               // row tiles (both sets), column tiles, k tiles
   int32_t kstr, zstr;               // LDS strides of the operand (bf16) and of Z (floats)
   int32_t grp0, ngrp;               // channel groups of this L
-  int32_t bt0;                      // first row-tile pointer of this L in bt_ptr
+  int32_t bt0;                      // first coefficient tile of this L; tile (rt, kt) is bt0 + rt * kt_n + kt
 };
 
 struct MixDev {
@@ -104,17 +110,16 @@ struct MixDev {
   const double* ynorm;
   MixL lv[2 * kMaxL + 1];   // host copy
   const MixL* lv_d;         // device copy (indexed by L in the kernel)
-  const int32_t* bt_ptr;   // per L: rt + 1 offsets into bt_kt / bt_idx
-  const int32_t* bt_kt;    // k tile of each stored tile
-  const int32_t* bt_idx;   // tile data index
-  const uint4* ctile;      // (2 * idx + split) * 64 + lane: 8 bf16 per lane
+  const uint4* ctile;      // dense tiles: (2 * tile + split) * 64 + lane, 8 bf16 per lane
   const int32_t* grp_pat;  // pattern of each group
-  const int4* grp_mem;     // 8 members per group: {row, A offset of a, A offset of b, 0}
+  const int4* grp_mem;     // 8 members per group: {row, A offset of a, A offset of b, la*5+lb}
   const int32_t* pat_hdr;  // 5 ints per pattern: la, lb, L, switch key, first coefficient
   const CgEnt* pat_ent;
   const float* pat_coef;   // coefficients per pattern over the selection-rule superset
   const int32_t* pat_off;  // first coefficient of pattern key la*45 + lb*9 + L (-1: invalid)
   const int32_t* rowtab;   // [L][a][p]: row of the coupled channel {a, p} in X_L, or -1
+  const int32_t* adj_ptr;  // [L][kMixWaves + 1]: each wavefront's adjoint units
+  const int4* adj_units;   // {l_t * 5 + l_p, first partner n, end partner n, l_t}
   int32_t tab_off;             // LDS: staged channel tables of one L (rows, groups)
   int32_t big_off, big_bytes;  // LDS layout
 };

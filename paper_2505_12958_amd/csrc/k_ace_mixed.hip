@@ -1,7 +1,7 @@
 // ACE part of the AP force, mixed-precision path.
 //
-// One workgroup (512 threads, 8 wavefronts, two per SIMD) evaluates a tile of 8 ACE-active
-// atoms taken from a global counter (persistent loop), entirely on chip:
+// One workgroup (1024 threads, 16 wavefronts, four per SIMD) evaluates tiles of 8 ACE-active
+// atoms (persistent loop, tiles assigned round-robin: every tile costs the same), on chip:
 //
 //  1. bond basis in FP32 from the FP64 minimum-image displacement; the
 //     atomic basis A_nlm of the 8 atoms is accumulated in LDS;
@@ -11,8 +11,8 @@
 //        Clebsch-Gordan entries are wavefront-uniform), written to LDS as a
 //        bf16 hi/lo split (x = hi + lo to ~16 bits);
 //     b. folded contraction Z_L = C_L X_L for both coefficient sets with
-//        v_mfma_f32_16x16x32_bf16: only non-zero 16x32 tiles of C_L are
-//        stored (pre-split into bf16 hi/lo), each product taken as
+//        v_mfma_f32_16x16x32_bf16: the 16x32 tiles of C_L are stored dense
+//        (pre-split into bf16 hi/lo), each product taken as
 //        hi*hi + hi*lo + lo*hi with FP32 accumulation;
 //     c. Z_L of each set goes to LDS (over the dead X_L) and the adjoint
 //        dphi/dA = (dX_L/dA)^T Z_L is formed per (channel, atom) and added
@@ -33,8 +33,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMT = 8;
-constexpr int kMThreads = 512;
-constexpr int kMWaves = kMThreads / 64;
+constexpr int kMWaves = kMixWaves;
+constexpr int kMThreads = 64 * kMWaves;
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -76,8 +76,9 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-// GEMM of one L: accumulators of the wavefront's row tiles (rt = wave + 8 i)
-// for all column tiles.  X is read from LDS (column-major, k contiguous).
+// GEMM of one L: accumulators of the wavefront's row tiles (rt = wave + kMWaves i)
+// for all column tiles.  X is read from LDS (column-major, k contiguous); the
+// coefficient tiles stream from L2, fetched one k tile ahead.
 template <int RTW, int CTN>
 __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const __bf16* xh,
                                            const __bf16* xl, f32x4 (&acc)[RTW][CTN], int wave,
@@ -87,57 +88,40 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
   for (int i = 0; i < RTW; ++i)
 #pragma unroll
     for (int c = 0; c < CTN; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int cur[RTW], end[RTW];
+  bool own[RTW];
+  const uint4* tp[RTW];
 #pragma unroll
   for (int i = 0; i < RTW; ++i) {
     const int rt = wave + kMWaves * i;
-    if (rt < rt_set) {
-      cur[i] = uni(as_const(m.bt_ptr)[P.bt0 + p * rt_set + rt]);
-      end[i] = uni(as_const(m.bt_ptr)[P.bt0 + p * rt_set + rt + 1]);
-    } else {
-      cur[i] = 0;
-      end[i] = 0;
-    }
+    own[i] = rt < rt_set;
+    tp[i] = m.ctile + (size_t)2 * 64 * ((size_t)P.bt0 + (size_t)(p * rt_set + (own[i] ? rt : 0)) * P.kt) + lane;
   }
   const int col_l = lane & 15;
   const int k_l = 8 * (lane >> 4);
-  // coefficient tiles of k tile kt for every owned row tile, one k tile ahead
   uint4 ch[RTW], cl[RTW], nh[RTW], nl[RTW];
-  bool nz[RTW], nn[RTW];
-  auto fetch = [&](int kt, uint4 (&h)[RTW], uint4 (&l)[RTW], bool (&f)[RTW]) {
 #pragma unroll
-    for (int i = 0; i < RTW; ++i) {
-      f[i] = kt < P.kt && cur[i] < end[i] && uni(as_const(m.bt_kt)[cur[i]]) == kt;
-      if (f[i]) {
-        const int idx = uni(as_const(m.bt_idx)[cur[i]]);
-        h[i] = m.ctile[(2 * (size_t)idx) * 64 + lane];
-        l[i] = m.ctile[(2 * (size_t)idx + 1) * 64 + lane];
-        ++cur[i];
-      }
-    }
-  };
-  fetch(0, ch, cl, nz);
+  for (int i = 0; i < RTW; ++i)
+    if (own[i]) { ch[i] = tp[i][0]; cl[i] = tp[i][64]; }
   for (int kt = 0; kt < P.kt; ++kt) {
-    fetch(kt + 1, nh, nl, nn);
-    bool any = false;
+    if (kt + 1 < P.kt) {
 #pragma unroll
-    for (int i = 0; i < RTW; ++i) any = any || nz[i];
-    if (any) {
+      for (int i = 0; i < RTW; ++i)
+        if (own[i]) { nh[i] = tp[i][128 * (kt + 1)]; nl[i] = tp[i][128 * (kt + 1) + 64]; }
+    }
 #pragma unroll
-      for (int c = 0; c < CTN; ++c) {
-        if (c >= P.ct) break;
-        const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
-        const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
-        const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
-        // the three split products, interleaved over independent accumulators
+    for (int c = 0; c < CTN; ++c) {
+      if (c >= P.ct) break;
+      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
+      const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
+      const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
+      // the three split products, interleaved over independent accumulators
 #pragma unroll
-        for (int sp = 0; sp < 3; ++sp) {
+      for (int sp = 0; sp < 3; ++sp) {
 #pragma unroll
-          for (int i = 0; i < RTW; ++i) {
-            if (!nz[i]) continue;
-            const bf16x8 a = as_bf16x8(sp == 2 ? cl[i] : ch[i]);
-            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? bl : bh, acc[i][c], 0, 0, 0);
-          }
+        for (int i = 0; i < RTW; ++i) {
+          if (!own[i]) continue;
+          const bf16x8 a = as_bf16x8(sp == 2 ? cl[i] : ch[i]);
+          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? bl : bh, acc[i][c], 0, 0, 0);
         }
       }
     }
@@ -145,7 +129,6 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
     for (int i = 0; i < RTW; ++i) {
       ch[i] = nh[i];
       cl[i] = nl[i];
-      nz[i] = nn[i];
     }
   }
 }
@@ -287,10 +270,10 @@ __device__ __forceinline__ void ad_all(std::integer_sequence<int, E...>, const f
 }
 
 // One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
-// coupling (n, LA) with (n', LB) to rank L.  Register indices are static;
-// the coupling coefficients are scalar loads.
+// coupling (n, LA) with (n', LB) to rank L.  Register indices and coupling
+// coefficients are compile-time constants.
 template <int LA, int LB, int L>
-__device__ __forceinline__ void xbuild_group(cptr<float> coef, const float* At, int4 mem,
+__device__ __forceinline__ void xbuild_group(const float* At, int4 mem,
                                              __bf16* xh, __bf16* xl, int kstr, int t) {
   float Aa[2 * LA + 1], Ab[2 * LB + 1], X[2 * L + 1];
 #pragma unroll
@@ -314,12 +297,14 @@ __device__ __forceinline__ void xbuild_group(cptr<float> coef, const float* At, 
 // One adjoint work unit: lane = (target n = lane/8, atom t = lane%8) with
 // target index a = (n, LT); partners (n', LP) for n' in [np0, np1).  Every
 // coupled channel {a, p} of this L is visited from both of its indices (the
-// coupled value is symmetric in them), so the lane owns its sums.
+// coupled value is symmetric in them), so the lane owns its sums.  The unit
+// with LT = L, LP = 0 and np0 = 0 also takes the A rows of X_L: dphi/dA_{n,L,M} gets
+// Z of row (n, L), and phi gets A.Z (summed over n for each atom).
 template <int LT, int LP, int L>
-__device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cptr<float> coef,
+__device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P,
                                              const float* At, const float* Z, float* omt,
-                                             const int32_t* rows_lds, int j, int t, int np0,
-                                             int np1) {
+                                             float* phi_t, const int32_t* rows_lds, int j, int t,
+                                             int np0, int np1) {
   constexpr int w = 2 * L + 1;
   const int lp1 = m.l_max + 1;
   const int nidx = m.n_max * lp1;
@@ -342,6 +327,23 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
     ad_all<LT, LP, L>(std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{},
                       Ap, Zv, ga);
   }
+  if constexpr (LT == L && LP == 0) {
+    if (np0 == 0 && P.arow) {
+      const int zb = (P.nch + (act ? j : 0)) * P.zstr + t * w;
+      float sa = 0.f;
+#pragma unroll
+      for (int q = 0; q < w; ++q) {
+        const float z = act ? Z[zb + q] : 0.f;
+        ga[q] += z;
+        sa = fmaf(At[(act ? j : 0) * m.nlm + L * L + q], z, sa);
+      }
+      // sum over the 8 lanes of atom t (lanes t, t + 8, ..., t + 56)
+      sa += __shfl_xor(sa, 8);
+      sa += __shfl_xor(sa, 16);
+      sa += __shfl_xor(sa, 32);
+      if (j == 0) atomicAdd(phi_t, sa);
+    }
+  }
   if (act) {
 #pragma unroll
     for (int q = 0; q <= 2 * LT; ++q) atomicAdd(omt + q, ga[q]);
@@ -351,12 +353,12 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
 #define AP_XB_CASE(la, lb)                                                           \
   case (la) * 5 + (lb):                                                              \
     if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
-      xbuild_group<la, lb, L>(coef, At, mem, xh, xl, kstr, t);                        \
+      xbuild_group<la, lb, L>(At, mem, xh, xl, kstr, t);                              \
     break;
 #define AP_AD_CASE(la, lb)                                                           \
   case (la) * 5 + (lb):                                                              \
     if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
-      adjoint_unit<la, lb, L>(m, P, coef, At, Z, omt, rows_lds, j, t, np0, np1);     \
+      adjoint_unit<la, lb, L>(m, P, At, Z, omt, phi_t, rows_lds, j, t, np0, np1);    \
     break;
 #define AP_ALL_CASES(X) \
   X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) \
@@ -364,6 +366,7 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P, cpt
   X(4, 0) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
 
 // Build the channel rows of X_L (bf16 hi/lo) for the 8 atoms of the tile.
+// Group g of this L: members {row, A offset of a, A offset of b, la*5+lb}.
 template <int L>
 __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const float* A, __bf16* xh,
                                        __bf16* xl, const int4* mem_lds, int wave, int lane) {
@@ -371,45 +374,34 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
   const float* At = A + t * m.apad;
   const int kstr = P.kstr;
   for (int g = wave; g < P.ngrp; g += kMWaves) {
-    const int gid = P.grp0 + g;
-    const int pat = uni(as_const(m.grp_pat)[gid]);
-    cptr<int32_t> hdr = as_const(m.pat_hdr) + 5 * pat;
-    const int la = uni(hdr[0]), lb = uni(hdr[1]);
-    cptr<float> coef = as_const(m.pat_coef) + uni(as_const(m.pat_off)[la * 45 + lb * 9 + L]);
     const int4 mem = mem_lds[g * 8 + j];
+    const int key = uni(mem.w);
     if (mem.x < 0) continue;
-    switch (la * 5 + lb) {
+    switch (key) {
       AP_ALL_CASES(AP_XB_CASE)
       default: break;
     }
   }
 }
 
-// Gradient of phi_p with respect to A from the coupled channels of X_L.
+// Gradient of phi_p with respect to A from the coupled channels of X_L.  The
+// wavefront's work units (target l, partner l, partner n range) come from a
+// schedule the library balanced over the workgroup's wavefronts.
 template <int L>
 __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
-                                        const float* Z, float* om, const int32_t* rows_lds,
-                                        int wave, int lane) {
-  const int lp1 = m.l_max + 1;
+                                        const float* Z, float* om, float* phi_p,
+                                        const int32_t* rows_lds, int wave, int lane) {
   const int j = lane >> 3, t = lane & 7;
+  float* phi_t = phi_p + 2 * t;
   const float* At = A + t * m.apad;
-  // units (l_target, l_partner, partner range): split partners when few
-  // (l, l') pairs are valid for this L, so every wavefront has work
-  int nvalid = 0;
-  for (int u = 0; u < lp1 * lp1; ++u) {
-    const int lt = u / lp1, lp = u % lp1;
-    if (iabs_c(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0) ++nvalid;
-  }
-  const int nsplit = nvalid >= kMWaves ? 1 : (nvalid * 2 >= kMWaves ? 2 : 4);
-  const int chunk = (m.n_max + nsplit - 1) / nsplit;
-  for (int u = wave; u < lp1 * lp1 * nsplit; u += kMWaves) {
-    const int pr = u / (lp1 * lp1), lt = (u / lp1) % lp1, lp = u % lp1;
-    if (!(iabs_c(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0)) continue;
-    const int np0 = pr * chunk, np1 = min(m.n_max, np0 + chunk);
-    if (np0 >= np1) continue;
-    cptr<float> coef = as_const(m.pat_coef) + uni(as_const(m.pat_off)[lt * 45 + lp * 9 + L]);
+  cptr<int32_t> ptr = as_const(m.adj_ptr) + L * (kMWaves + 1);
+  const int u0 = uni(ptr[wave]), u1 = uni(ptr[wave + 1]);
+  cptr<int32_t> units = as_const(reinterpret_cast<const int32_t*>(m.adj_units));
+  for (int u = u0; u < u1; ++u) {
+    const int key = uni(units[4 * u]), np0 = uni(units[4 * u + 1]), np1 = uni(units[4 * u + 2]),
+              lt = uni(units[4 * u + 3]);
     float* omt = om + t * m.apad + j * m.nlm + lt * lt;
-    switch (lt * 5 + lp) {
+    switch (key) {
       AP_ALL_CASES(AP_AD_CASE)
       default: break;
     }
@@ -430,13 +422,23 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
   __bf16* xl = xh + (size_t)P.ct * 16 * P.kstr;
   float* Z = reinterpret_cast<float*>(big);
   for (int p = 0; p < 2; ++p) {
-    // coupled operand X_L (zero padding, channel rows, A rows, constant row)
+    // coupled operand X_L: zero padding (rows past nrow up to the k tiles,
+    // columns past the tile's atoms), channel rows, A rows, constant row
     {
-      uint4* z4 = reinterpret_cast<uint4*>(big);
-      const int n16 = (P.ct * 16 * P.kstr * 2 * 2) / 16;
-      for (int q = tid; q < n16; q += kMThreads) z4[q] = uint4{0u, 0u, 0u, 0u};
+      const int kpad = P.kt * 32;
+      const int padr = kpad - P.nrow;
+      for (int q = tid; q < ncols * padr; q += kMThreads) {
+        const int o = (q / padr) * P.kstr + P.nrow + q % padr;
+        xh[o] = (__bf16)0.0f;
+        xl[o] = (__bf16)0.0f;
+      }
+      const int padc = P.ct * 16 - ncols;
+      for (int q = tid; q < padc * kpad; q += kMThreads) {
+        const int o = (ncols + q / kpad) * P.kstr + q % kpad;
+        xh[o] = (__bf16)0.0f;
+        xl[o] = (__bf16)0.0f;
+      }
     }
-    __syncthreads();
     xbuild<L>(m, P, A, xh, xl, mem_lds, wave, lane);
     if (P.arow) {
       for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
@@ -460,18 +462,8 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
     store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
     __syncthreads();
     float* om = p == 0 ? om1 : om2;
-    adjoint<L>(m, P, A, Z, om, rows_lds, wave, lane);
+    adjoint<L>(m, P, A, Z, om, phi_lds + p, rows_lds, wave, lane);
     if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
-    // A rows: phi += A Z, dphi/dA += Z
-    if (P.arow) {
-      for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
-        const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
-        const int ai = t * m.apad + n * m.nlm + L * L + M;
-        const float z = Z[(P.nch + n) * P.zstr + col];
-        atomicAdd(&om[ai], z);
-        atomicAdd(&phi_lds[t * 2 + p], A[ai] * z);
-      }
-    }
     __syncthreads();
   }
 }
@@ -556,17 +548,17 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 template <int L, int RTW, int CTN>
 __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     MixDev m, const int32_t* __restrict__ n_ace_p, int n_all, const float* __restrict__ A_in,
-    int32_t* __restrict__ counter, float* __restrict__ om_buf, float* __restrict__ phi_buf) {
+    float* __restrict__ om_buf, float* __restrict__ phi_buf) {
   extern __shared__ __align__(16) unsigned char lds[];
   float* A = reinterpret_cast<float*>(lds);
   float* om1 = A + kMT * m.apad;
   float* om2 = om1 + kMT * m.apad;
   float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2]
   unsigned char* big = lds + m.big_off;
-  __shared__ int s_tile;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
   const int n_items = n_ace_p ? *n_ace_p : n_all;
+  const int n_tiles = (n_items + kMT - 1) / kMT;
   const MixL P = load_level(m.lv_d + L);
   // stage this rank's channel tables in LDS (read by every tile)
   const int nidx = m.n_max * (m.l_max + 1);
@@ -574,36 +566,32 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
   for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
-  for (;;) {
-    if (tid == 0) s_tile = atomicAdd(counter + L, 1);
-    __syncthreads();
-    const int tile = s_tile;
-    if (tile * kMT >= n_items) break;
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int nt = min(kMT, n_items - tile * kMT);
-    for (int q = tid; q < 3 * kMT * m.apad + 2 * kMT; q += kMThreads) A[q] = 0.f;
-    __syncthreads();
-    for (int q = tid; q < nt * m.nA; q += kMThreads) {
-      const int t = q / m.nA, e = q % m.nA;
-      A[t * m.apad + e] = A_in[(int64_t)(tile * kMT) * m.nA + q];
+    const int64_t base = (int64_t)tile * kMT * m.nA;
+    // A of the tile's atoms, and the gradient and phi sums of the lower ranks
+    for (int q = tid; q < kMT * m.apad; q += kMThreads) {
+      const int t = q / m.apad, e = q - t * m.apad;
+      const bool ok = t < nt && e < m.nA;
+      const int64_t o = base + (int64_t)t * m.nA + e;
+      A[q] = ok ? A_in[o] : 0.f;
+      float2 old = make_float2(0.f, 0.f);
+      if (L > 0 && ok) old = reinterpret_cast<const float2*>(om_buf)[o];
+      om1[q] = old.x;
+      om2[q] = old.y;
+    }
+    if (tid < 2 * kMT) {
+      const int64_t o = (int64_t)tile * kMT * 2 + tid;
+      phi_lds[tid] = (L > 0 && tid < 2 * nt) ? phi_buf[o] : 0.f;
     }
     __syncthreads();
     rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
     __syncthreads();
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
-      const int t = q / m.nA, e = q % m.nA;
-      const int64_t o = (int64_t)(tile * kMT) * m.nA + q;
-      float2 v = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
-      if (L > 0) {
-        const float2 old = reinterpret_cast<const float2*>(om_buf)[o];
-        v.x += old.x;
-        v.y += old.y;
-      }
-      reinterpret_cast<float2*>(om_buf)[o] = v;
+      const int t = q / m.nA, e = q - t * m.nA;
+      reinterpret_cast<float2*>(om_buf)[base + q] = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
     }
-    if (tid < 2 * nt) {
-      const int64_t o = (int64_t)tile * kMT * 2 + tid;
-      phi_buf[o] = (L > 0 ? phi_buf[o] : 0.f) + phi_lds[tid];
-    }
+    if (tid < 2 * nt) phi_buf[(int64_t)tile * kMT * 2 + tid] = phi_lds[tid];
     __syncthreads();
   }
 }
@@ -723,27 +711,27 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     int dev = 0, n_cu = 256;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e = launch_fill_i32(counter, 0, 2 * kMaxL + 1, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    (void)counter;
     const size_t lds = ace_mixed_lds_bytes(m);
     const int32_t* na = ace_list ? n_ace : nullptr;
     for (int L = 0; L <= m.L_max; ++L) {
       const void* fn = nullptr;
       switch (L) {
-        case 0: fn = (const void*)k_ace_rank<0, 3, 1>; break;
-        case 1: fn = (const void*)k_ace_rank<1, 3, 2>; break;
-        case 2: fn = (const void*)k_ace_rank<2, 3, 3>; break;
-        case 3: fn = (const void*)k_ace_rank<3, 3, 4>; break;
-        case 4: fn = (const void*)k_ace_rank<4, 3, 5>; break;
-        case 5: fn = (const void*)k_ace_rank<5, 2, 6>; break;
-        case 6: fn = (const void*)k_ace_rank<6, 2, 7>; break;
-        case 7: fn = (const void*)k_ace_rank<7, 1, 8>; break;
-        default: fn = (const void*)k_ace_rank<8, 1, 9>; break;
+        case 0: fn = (const void*)k_ace_rank<0, kMixRtw[0], 1>; break;
+        case 1: fn = (const void*)k_ace_rank<1, kMixRtw[1], 2>; break;
+        case 2: fn = (const void*)k_ace_rank<2, kMixRtw[2], 3>; break;
+        case 3: fn = (const void*)k_ace_rank<3, kMixRtw[3], 4>; break;
+        case 4: fn = (const void*)k_ace_rank<4, kMixRtw[4], 5>; break;
+        case 5: fn = (const void*)k_ace_rank<5, kMixRtw[5], 6>; break;
+        case 6: fn = (const void*)k_ace_rank<6, kMixRtw[6], 7>; break;
+        case 7: fn = (const void*)k_ace_rank<7, kMixRtw[7], 8>; break;
+        default: fn = (const void*)k_ace_rank<8, kMixRtw[8], 9>; break;
       }
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
-      void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&counter,
-                      (void*)&om_buf, (void*)&phi_buf};
+      void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&om_buf,
+                      (void*)&phi_buf};
       e = hipLaunchKernel(fn, dim3(n_cu), dim3(kMThreads), args, lds, s);
       if (e != hipSuccess) return e;
     }
