@@ -570,7 +570,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     P.ct = (8 * w + 15) / 16;
     P.rt = 2 * P.nrow16 / 16;
     P.zstr = 8 * w + 1;
-    if ((P.nrow16 / 16 + kMixWaves - 1) / kMixWaves > kMixRtw[L] || P.ct > L + 1 || nmax > 8)
+    if ((P.nrow16 / 16 + kMixWaves - 1) / kMixWaves > kMixRtw[L] || P.ct != L + 1 || nmax > 8)
       return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model outside the mixed kernels' tiling (n_max <= 8, rows per rank)");
     big = std::max(big, (size_t)P.ct * 16 * P.kstr * 2 * 2);
     big = std::max(big, (size_t)P.nrow * P.zstr * 4);

@@ -92,8 +92,8 @@ struct CgEnt {
 // Work-group shape of the mixed rank kernels: kMixWaves wavefronts; each
 // owns at most kMixRtw[L] 16-row tiles of one coefficient set of C_L
 // (row tile rt = wave + kMixWaves * i).
-constexpr int kMixWaves = 12;
-constexpr int kMixRtw[2 * kMaxL + 1] = {1, 2, 2, 2, 2, 1, 1, 1, 1};
+constexpr int kMixWaves = 8;
+constexpr int kMixRtw[2 * kMaxL + 1] = {2, 3, 3, 3, 3, 2, 2, 1, 1};
 
 struct MixL {
   int32_t nrow, nrow16, nch, arow;  // rows of X_L, padded to 16, channel rows, has A rows

@@ -1,6 +1,6 @@
 // ACE part of the AP force, mixed-precision path.
 //
-// One workgroup (1024 threads, 16 wavefronts, four per SIMD) evaluates tiles of 8 ACE-active
+// One workgroup (512 threads, 8 wavefronts, two per SIMD) evaluates tiles of 8 ACE-active
 // atoms (persistent loop, tiles assigned round-robin: every tile costs the same), on chip:
 //
 //  1. bond basis in FP32 from the FP64 minimum-image displacement; the
@@ -110,7 +110,6 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
     }
 #pragma unroll
     for (int c = 0; c < CTN; ++c) {
-      if (c >= P.ct) break;
       const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
       const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
       const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
@@ -147,7 +146,6 @@ __device__ __forceinline__ void store_z(const MixL& P, const f32x4 (&acc)[RTW][C
     const int row0 = rt * 16 + r_l;
 #pragma unroll
     for (int c = 0; c < CTN; ++c) {
-      if (c >= P.ct) break;
       const int col = c * 16 + col_l;
       if (col >= ncols) continue;
 #pragma unroll
@@ -566,32 +564,64 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
   for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
+  // A of a tile's atoms and the gradient and phi sums of the lower ranks: the
+  // loads of the next tile are issued before the stores of the current one
+  // (registers are free there), so their latency overlaps the stores
+  constexpr int kPf = (kMT * (8 * kMaxLM + 1) + kMThreads - 1) / kMThreads;
+  float pa[kPf];
+  float2 po[kPf];
+  float pphi = 0.f;
+  auto fetch = [&](int tile) {
+    const int nt = min(kMT, n_items - tile * kMT);
+    const int64_t base = (int64_t)tile * kMT * m.nA;
+    // the index arithmetic below is redone per tile rather than kept live
+    // across the whole tile loop (registers are scarce in rank_L)
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+#pragma unroll
+    for (int r = 0; r < kPf; ++r) {
+      const int q = tq + r * kMThreads;
+      const int t = q / m.apad, e = q - t * m.apad;
+      const bool ok = q < kMT * m.apad && t < nt && e < m.nA;
+      const int64_t o = base + (int64_t)t * m.nA + e;
+      pa[r] = ok ? A_in[o] : 0.f;
+      po[r] = (L > 0 && ok) ? reinterpret_cast<const float2*>(om_buf)[o] : make_float2(0.f, 0.f);
+    }
+    if (tid < 2 * kMT) pphi = (L > 0 && tid < 2 * nt) ? phi_buf[(int64_t)tile * kMT * 2 + tid] : 0.f;
+  };
+  auto stage = [&]() {
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+#pragma unroll
+    for (int r = 0; r < kPf; ++r) {
+      const int q = tq + r * kMThreads;
+      if (q < kMT * m.apad) {
+        A[q] = pa[r];
+        om1[q] = po[r].x;
+        om2[q] = po[r].y;
+      }
+    }
+    if (tid < 2 * kMT) phi_lds[tid] = pphi;
+  };
+  if ((int)blockIdx.x < n_tiles) {
+    fetch(blockIdx.x);
+    stage();
+  }
+  __syncthreads();
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int nt = min(kMT, n_items - tile * kMT);
     const int64_t base = (int64_t)tile * kMT * m.nA;
-    // A of the tile's atoms, and the gradient and phi sums of the lower ranks
-    for (int q = tid; q < kMT * m.apad; q += kMThreads) {
-      const int t = q / m.apad, e = q - t * m.apad;
-      const bool ok = t < nt && e < m.nA;
-      const int64_t o = base + (int64_t)t * m.nA + e;
-      A[q] = ok ? A_in[o] : 0.f;
-      float2 old = make_float2(0.f, 0.f);
-      if (L > 0 && ok) old = reinterpret_cast<const float2*>(om_buf)[o];
-      om1[q] = old.x;
-      om2[q] = old.y;
-    }
-    if (tid < 2 * kMT) {
-      const int64_t o = (int64_t)tile * kMT * 2 + tid;
-      phi_lds[tid] = (L > 0 && tid < 2 * nt) ? phi_buf[o] : 0.f;
-    }
-    __syncthreads();
     rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
     __syncthreads();
+    const int next = tile + (int)gridDim.x;
+    if (next < n_tiles) fetch(next);
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
       const int t = q / m.nA, e = q - t * m.nA;
       reinterpret_cast<float2*>(om_buf)[base + q] = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
     }
     if (tid < 2 * nt) phi_buf[(int64_t)tile * kMT * 2 + tid] = phi_lds[tid];
+    __syncthreads();
+    if (next < n_tiles) stage();
     __syncthreads();
   }
 }
