@@ -76,9 +76,61 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-// GEMM of one L: accumulators of the wavefront's row tiles (rt = wave + kMWaves i)
-// for all column tiles.  X is read from LDS (column-major, k contiguous); the
-// coefficient tiles stream from L2, fetched one k tile ahead.
+// GEMM of one L for N owned row tiles (rt = wave + kMWaves i, i < N): N and
+// CTN are compile-time, so the k loop has no branches and the coefficient
+// loads of the next k tile stay in flight under this tile's MFMAs.  X is read
+// from LDS (column-major, k contiguous); the coefficient tiles stream from L2.
+template <int N, int RTW, int CTN>
+__device__ __forceinline__ void gemm_owned(const MixL& P, const uint4* base, const __bf16* xh,
+                                           const __bf16* xl, f32x4 (&acc)[RTW][CTN], int lane) {
+  static_assert(N >= 1 && N <= RTW, "owned row tiles");
+  const uint4* tp[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) tp[i] = base + (size_t)2 * 64 * kMWaves * i * P.kt;
+  const int col_l = lane & 15;
+  const int k_l = 8 * (lane >> 4);
+  // two register buffers of coefficient tiles (hi, lo), ping-pong: the tiles
+  // of k tile kt + 1 load while those of kt feed the MFMAs
+  uint4 ah[N], al[N], bh[N], bl[N];
+  auto load = [&](uint4 (&h)[N], uint4 (&l)[N], int kt) {
+    const int k = min(kt, P.kt - 1);  // past the end: reload the last tile (harmless)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      h[i] = tp[i][128 * k];
+      l[i] = tp[i][128 * k + 64];
+    }
+    // compiler barrier: keep the loads here, ahead of their use
+    asm volatile("" ::: "memory");
+  };
+  auto compute = [&](const uint4 (&h)[N], const uint4 (&l)[N], int kt) {
+#pragma unroll
+    for (int c = 0; c < CTN; ++c) {
+      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
+      const bf16x8 xbh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
+      const bf16x8 xbl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
+      // the three split products, interleaved over independent accumulators
+#pragma unroll
+      for (int sp = 0; sp < 3; ++sp) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const bf16x8 a = as_bf16x8(sp == 2 ? l[i] : h[i]);
+          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? xbl : xbh, acc[i][c], 0, 0, 0);
+        }
+      }
+    }
+  };
+  load(ah, al, 0);
+  for (int kt = 0; kt < P.kt; kt += 2) {
+    load(bh, bl, kt + 1);
+    compute(ah, al, kt);
+    if (kt + 1 < P.kt) {
+      load(ah, al, kt + 2);
+      compute(bh, bl, kt + 1);
+    }
+  }
+}
+
+// GEMM of one L: accumulators of the wavefront's row tiles for all column tiles.
 template <int RTW, int CTN>
 __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const __bf16* xh,
                                            const __bf16* xl, f32x4 (&acc)[RTW][CTN], int wave,
@@ -88,48 +140,13 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
   for (int i = 0; i < RTW; ++i)
 #pragma unroll
     for (int c = 0; c < CTN; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bool own[RTW];
-  const uint4* tp[RTW];
-#pragma unroll
-  for (int i = 0; i < RTW; ++i) {
-    const int rt = wave + kMWaves * i;
-    own[i] = rt < rt_set;
-    tp[i] = m.ctile + (size_t)2 * 64 * ((size_t)P.bt0 + (size_t)(p * rt_set + (own[i] ? rt : 0)) * P.kt) + lane;
-  }
-  const int col_l = lane & 15;
-  const int k_l = 8 * (lane >> 4);
-  uint4 ch[RTW], cl[RTW], nh[RTW], nl[RTW];
-#pragma unroll
-  for (int i = 0; i < RTW; ++i)
-    if (own[i]) { ch[i] = tp[i][0]; cl[i] = tp[i][64]; }
-  for (int kt = 0; kt < P.kt; ++kt) {
-    if (kt + 1 < P.kt) {
-#pragma unroll
-      for (int i = 0; i < RTW; ++i)
-        if (own[i]) { nh[i] = tp[i][128 * (kt + 1)]; nl[i] = tp[i][128 * (kt + 1) + 64]; }
-    }
-#pragma unroll
-    for (int c = 0; c < CTN; ++c) {
-      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
-      const bf16x8 bh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
-      const bf16x8 bl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
-      // the three split products, interleaved over independent accumulators
-#pragma unroll
-      for (int sp = 0; sp < 3; ++sp) {
-#pragma unroll
-        for (int i = 0; i < RTW; ++i) {
-          if (!own[i]) continue;
-          const bf16x8 a = as_bf16x8(sp == 2 ? cl[i] : ch[i]);
-          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? bl : bh, acc[i][c], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RTW; ++i) {
-      ch[i] = nh[i];
-      cl[i] = nl[i];
-    }
-  }
+  const int nown = uni(min(RTW, max(0, (rt_set - wave + kMWaves - 1) / kMWaves)));
+  const uint4* base = m.ctile + (size_t)2 * 64 * ((size_t)P.bt0 + (size_t)(p * rt_set + wave) * P.kt) + lane;
+  if (nown == 1) gemm_owned<1, RTW, CTN>(P, base, xh, xl, acc, lane);
+  if constexpr (RTW >= 2)
+    if (nown == 2) gemm_owned<(RTW >= 2 ? 2 : 1), RTW, CTN>(P, base, xh, xl, acc, lane);
+  if constexpr (RTW >= 3)
+    if (nown == 3) gemm_owned<(RTW >= 3 ? 3 : 1), RTW, CTN>(P, base, xh, xl, acc, lane);
 }
 
 // Write the accumulators of coefficient set p (rows [p*nrow16, (p+1)*nrow16))
