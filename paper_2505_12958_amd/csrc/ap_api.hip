@@ -655,57 +655,87 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     }
     P.ngrp = (int32_t)grp_pat.size() - P.grp0;
   }
-  // adjoint work units per L: (target l, partner l, range of partner n),
-  // cost-balanced over the workgroup's wavefronts (largest first onto the
-  // least-loaded wavefront); cost per partner ~ 2 nnz(CG) + 24
+  // adjoint jobs per L: (target l, component part K of NP) - every job owns
+  // its gradient entries, so no two wavefronts write the same entry.  The
+  // part counts and the assignment to wavefronts balance an estimated cost
+  // (largest job first onto the least-loaded wavefront).
   std::vector<int32_t> adj_ptr;
   std::vector<int4> adj_units;
   for (int L = 0; L <= Lmax; ++L) {
-    struct Unit { int key, np0, np1, lt; double cost; };
-    std::vector<Unit> pats;
-    double total = 0;
-    for (int lt = 0; lt <= lmax; ++lt)
+    const int w = 2 * L + 1;
+    // cost of the components [i0, i1) of target l = lt
+    auto job_cost = [&](int lt, int i0, int i1) {
+      double c = 0;
       for (int lp = 0; lp <= lmax; ++lp) {
         if (!(std::abs(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0)) continue;
-        bool any = false;
-        for (int na = 0; na < nmax && !any; ++na)
-          for (int nb = 0; nb < nmax && !any; ++nb)
-            any = rowtab[((size_t)L * nidx + na * lp1 + lt) * nidx + nb * lp1 + lp] >= 0;
-        // (L, 0) always has a unit: it also carries the A rows of X_L
-        if (!any && !(lt == L && lp == 0 && L <= lmax)) continue;
         const auto& C = cgcache[std::make_tuple(lt, lp, L)];
+        const int w2 = 2 * lp + 1;
         int nnz = 0;
-        for (double c : C) nnz += c != 0.0;
-        const double c1 = 2.0 * nnz + 24.0;
-        pats.push_back(Unit{lt * 5 + lp, 0, nmax, lt, c1 * nmax});
-        total += c1 * nmax;
+        for (int p1 = i0; p1 < i1; ++p1)
+          for (int q = 0; q < w2; ++q)
+            for (int M = 0; M < w; ++M) nnz += C[((size_t)p1 * w2 + q) * w + M] != 0.0;
+        c += nmax * (2.0 * nnz + w + w2 + 8.0);
       }
-    (void)total;
-    // few units (every unit ends with one LDS atomic add per output): split the
-    // costliest partner range in two until there are as many units as wavefronts
-    std::vector<Unit> units = pats;
-    while ((int)units.size() < kMixWaves) {
-      int best = -1;
-      for (int k = 0; k < (int)units.size(); ++k)
-        if (units[k].np1 - units[k].np0 > 1 && (best < 0 || units[k].cost > units[best].cost)) best = k;
-      if (best < 0) break;
-      Unit u = units[best];
-      const int mid = (u.np0 + u.np1) / 2;
-      const double per = u.cost / (u.np1 - u.np0);
-      units[best] = Unit{u.key, u.np0, mid, u.lt, per * (mid - u.np0)};
-      units.push_back(Unit{u.key, mid, u.np1, u.lt, per * (u.np1 - mid)});
+      if (lt == L) c += 3.0 * (i1 - i0) + 12.0;
+      return c;
+    };
+    std::vector<int> np(lmax + 1, 1);
+    std::vector<bool> live(lmax + 1, false);
+    for (int lt = 0; lt <= lmax; ++lt) {
+      bool any = lt == L;
+      for (int lp = 0; lp <= lmax && !any; ++lp)
+        if (std::abs(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0) any = true;
+      live[lt] = any;
     }
-    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
-    std::vector<std::vector<Unit>> per(kMixWaves);
-    std::vector<double> load(kMixWaves, 0.0);
-    for (auto& u : units) {
-      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      per[w].push_back(u);
-      load[w] += u.cost;
+    struct Job { int lt, npart, k; double cost; };
+    auto schedule = [&](std::vector<std::vector<Job>>& per) {
+      std::vector<Job> jobs;
+      for (int lt = 0; lt <= lmax; ++lt) {
+        if (!live[lt]) continue;
+        const int nc = 2 * lt + 1;
+        for (int k = 0; k < np[lt]; ++k)
+          jobs.push_back(Job{lt, np[lt], k, job_cost(lt, k * nc / np[lt], (k + 1) * nc / np[lt])});
+      }
+      std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
+      per.assign(kMixWaves, {});
+      std::vector<double> load(kMixWaves, 0.0);
+      for (auto& jb : jobs) {
+        const int wv = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        per[wv].push_back(jb);
+        load[wv] += jb.cost;
+      }
+      return *std::max_element(load.begin(), load.end());
+    };
+    std::vector<std::vector<Job>> per;
+    double best = schedule(per);
+    for (;;) {
+      // split further the target whose job sits on the most loaded wavefront
+      int wmax = 0;
+      double lmax_w = -1;
+      for (int wv = 0; wv < kMixWaves; ++wv) {
+        double l = 0;
+        for (auto& jb : per[wv]) l += jb.cost;
+        if (l > lmax_w) { lmax_w = l; wmax = wv; }
+      }
+      int cand = -1;
+      double cc = -1;
+      for (auto& jb : per[wmax])
+        if (np[jb.lt] < 3 && np[jb.lt] < 2 * jb.lt + 1 && jb.cost > cc) { cc = jb.cost; cand = jb.lt; }
+      if (cand < 0) break;
+      ++np[cand];
+      std::vector<std::vector<Job>> trial;
+      const double t = schedule(trial);
+      if (t < best) {
+        best = t;
+        per = trial;
+      } else {
+        --np[cand];
+        break;
+      }
     }
-    for (int w = 0; w < kMixWaves; ++w) {
+    for (int wv = 0; wv < kMixWaves; ++wv) {
       adj_ptr.push_back((int32_t)adj_units.size());
-      for (auto& u : per[w]) adj_units.push_back(make_int4(u.key, u.np0, u.np1, u.lt));
+      for (auto& jb : per[wv]) adj_units.push_back(make_int4(jb.lt * 16 + jb.npart * 4 + jb.k, 0, 0, jb.lt));
     }
     adj_ptr.push_back((int32_t)adj_units.size());
   }

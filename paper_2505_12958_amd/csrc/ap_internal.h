@@ -119,7 +119,7 @@ struct MixDev {
   const int32_t* pat_off;  // first coefficient of pattern key la*45 + lb*9 + L (-1: invalid)
   const int32_t* rowtab;   // [L][a][p]: row of the coupled channel {a, p} in X_L, or -1
   const int32_t* adj_ptr;  // [L][kMixWaves + 1]: each wavefront's adjoint units
-  const int4* adj_units;   // {l_t * 5 + l_p, first partner n, end partner n, l_t}
+  const int4* adj_units;   // {l_t * 16 + parts * 4 + part, 0, 0, l_t}
   int32_t tab_off;             // LDS: staged channel tables of one L (rows, groups)
   int32_t big_off, big_bytes;  // LDS layout
 };

@@ -264,13 +264,13 @@ __device__ __forceinline__ void xb_entry(const float* Aa, const float* Ab, float
     if constexpr (c != 0.0f) X[q] = fmaf(c * Aa[i1], Ab[i2], X[q]);
   }
 }
-template <int LT, int LP, int L, int E>
+template <int LT, int LP, int L, int I0, int I1, int E>
 __device__ __forceinline__ void ad_entry(const float* Ap, const float* Zv, float* ga) {
   constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LP + 1),
                 i1 = E / ((2 * L + 1) * (2 * LP + 1));
-  if constexpr (cg_rule(i1 - LT, i2 - LP, q - L)) {
+  if constexpr (i1 >= I0 && i1 < I1 && cg_rule(i1 - LT, i2 - LP, q - L)) {
     constexpr float c = (float)ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L);
-    if constexpr (c != 0.0f) ga[i1] = fmaf(c * Ap[i2], Zv[q], ga[i1]);
+    if constexpr (c != 0.0f) ga[i1 - I0] = fmaf(c * Ap[i2], Zv[q], ga[i1 - I0]);
   }
 }
 template <int LA, int LB, int L, int... E>
@@ -278,10 +278,10 @@ __device__ __forceinline__ void xb_all(std::integer_sequence<int, E...>, const f
                                        const float* Ab, float* X) {
   (xb_entry<LA, LB, L, E>(Aa, Ab, X), ...);
 }
-template <int LT, int LP, int L, int... E>
+template <int LT, int LP, int L, int I0, int I1, int... E>
 __device__ __forceinline__ void ad_all(std::integer_sequence<int, E...>, const float* Ap,
                                        const float* Zv, float* ga) {
-  (ad_entry<LT, LP, L, E>(Ap, Zv, ga), ...);
+  (ad_entry<LT, LP, L, I0, I1, E>(Ap, Zv, ga), ...);
 }
 
 // One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
@@ -309,29 +309,28 @@ __device__ __forceinline__ void xbuild_group(const float* At, int4 mem,
   }
 }
 
-// One adjoint work unit: lane = (target n = lane/8, atom t = lane%8) with
-// target index a = (n, LT); partners (n', LP) for n' in [np0, np1).  Every
-// coupled channel {a, p} of this L is visited from both of its indices (the
-// coupled value is symmetric in them), so the lane owns its sums.  The unit
-// with LT = L, LP = 0 and np0 = 0 also takes the A rows of X_L: dphi/dA_{n,L,M} gets
-// Z of row (n, L), and phi gets A.Z (summed over n for each atom).
-template <int LT, int LP, int L>
-__device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P,
-                                             const float* At, const float* Z, float* omt,
-                                             float* phi_t, const int32_t* rows_lds, int j, int t,
-                                             int np0, int np1) {
+// Adjoint of one coupled pattern (LT, LP, L) for the components [I0, I1) of
+// the target: lane = (target n = lane/8, atom t = lane%8), target index
+// a = (n, LT), partners (n', LP) for every n'.  Every coupled channel {a, p}
+// of this L is visited from both of its indices (the coupled value is
+// symmetric in them), so the lane owns its sums.
+template <int LT, int LP, int L, int I0, int I1>
+__device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P, const float* At,
+                                                 const float* Z, const int32_t* rows_lds, int j,
+                                                 int t, float* ga) {
   constexpr int w = 2 * L + 1;
   const int lp1 = m.l_max + 1;
   const int nidx = m.n_max * lp1;
   const bool act = j < m.n_max;
   const int a = j * lp1 + LT;
-  float ga[2 * LT + 1];
-#pragma unroll
-  for (int q = 0; q <= 2 * LT; ++q) ga[q] = 0.f;
-  for (int np = np0; np < np1; ++np) {
+  // the channel row of the next partner is fetched one partner ahead
+  const int32_t* rp = rows_lds + a * nidx + LP;
+  int row_next = act ? rp[0] : -1;
+#pragma unroll 1
+  for (int np = 0; np < m.n_max; ++np) {
     const int pidx = np * lp1 + LP;
-    const int row = act ? rows_lds[a * nidx + pidx] : -1;
-    if (__ballot(row >= 0) == 0ull) continue;
+    const int row = row_next;
+    row_next = (act && np + 1 < m.n_max) ? rp[(np + 1) * lp1] : -1;
     float Ap[2 * LP + 1], Zv[w];
 #pragma unroll
     for (int q = 0; q <= 2 * LP; ++q) Ap[q] = At[np * m.nlm + LP * LP + q];
@@ -339,17 +338,47 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P,
     const int zb = (row < 0 ? 0 : row) * P.zstr + t * w;
 #pragma unroll
     for (int q = 0; q < w; ++q) Zv[q] = f * Z[zb + q];
-    ad_all<LT, LP, L>(std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{},
-                      Ap, Zv, ga);
+    ad_all<LT, LP, L, I0, I1>(
+        std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{}, Ap, Zv, ga);
   }
-  if constexpr (LT == L && LP == 0) {
-    if (np0 == 0 && P.arow) {
+}
+
+template <int LT, int L, int I0, int I1, int LP>
+__device__ __forceinline__ void adjoint_lp(const MixDev& m, const MixL& P, const float* At,
+                                           const float* Z, const int32_t* rows_lds, int j, int t,
+                                           float* ga) {
+  if constexpr (LP <= kMaxL) {
+    if constexpr (iabs_c(LT - LP) <= L && L <= LT + LP && ((LT + LP + L) & 1) == 0) {
+      if (LP <= m.l_max) adjoint_partners<LT, LP, L, I0, I1>(m, P, At, Z, rows_lds, j, t, ga);
+    }
+    adjoint_lp<LT, L, I0, I1, LP + 1>(m, P, At, Z, rows_lds, j, t, ga);
+  }
+}
+
+// One adjoint job: the components [K (2LT+1)/NP, (K+1)(2LT+1)/NP) of every
+// target (n, LT), summed over all partner patterns; jobs write disjoint
+// gradient entries, so the sums are stored without atomics.  The job with
+// LT = L also takes the A rows of X_L: dphi/dA_{n,L,M} gets Z of row (n, L)
+// and phi gets A.Z (summed over n for each atom).
+template <int LT, int L, int NP, int K>
+__device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, const float* At,
+                                            const float* Z, float* omt, float* phi_t,
+                                            const int32_t* rows_lds, int j, int t) {
+  constexpr int w = 2 * L + 1;
+  constexpr int I0 = K * (2 * LT + 1) / NP, I1 = (K + 1) * (2 * LT + 1) / NP;
+  const bool act = j < m.n_max;
+  float ga[I1 - I0 > 0 ? I1 - I0 : 1];
+#pragma unroll
+  for (int q = 0; q < I1 - I0; ++q) ga[q] = 0.f;
+  adjoint_lp<LT, L, I0, I1, 0>(m, P, At, Z, rows_lds, j, t, ga);
+  if constexpr (LT == L) {
+    if (P.arow) {
       const int zb = (P.nch + (act ? j : 0)) * P.zstr + t * w;
       float sa = 0.f;
 #pragma unroll
-      for (int q = 0; q < w; ++q) {
+      for (int q = I0; q < I1; ++q) {
         const float z = act ? Z[zb + q] : 0.f;
-        ga[q] += z;
+        ga[q - I0] += z;
         sa = fmaf(At[(act ? j : 0) * m.nlm + L * L + q], z, sa);
       }
       // sum over the 8 lanes of atom t (lanes t, t + 8, ..., t + 56)
@@ -361,7 +390,7 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P,
   }
   if (act) {
 #pragma unroll
-    for (int q = 0; q <= 2 * LT; ++q) atomicAdd(omt + q, ga[q]);
+    for (int q = I0; q < I1; ++q) omt[q] += ga[q - I0];
   }
 }
 
@@ -370,11 +399,13 @@ __device__ __forceinline__ void adjoint_unit(const MixDev& m, const MixL& P,
     if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
       xbuild_group<la, lb, L>(At, mem, xh, xl, kstr, t);                              \
     break;
-#define AP_AD_CASE(la, lb)                                                           \
-  case (la) * 5 + (lb):                                                              \
-    if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
-      adjoint_unit<la, lb, L>(m, P, At, Z, omt, phi_t, rows_lds, j, t, np0, np1);    \
+#define AP_AD_CASE(lt, np, k)                                                        \
+  case (lt) * 16 + (np) * 4 + (k):                                                   \
+    if constexpr ((k) < (np) && (np) <= 2 * (lt) + 1)                                \
+      adjoint_job<lt, L, np, k>(m, P, At, Z, omt, phi_t, rows_lds, j, t);            \
     break;
+#define AP_AD_LT(lt) AP_AD_CASE(lt, 1, 0) AP_AD_CASE(lt, 2, 0) AP_AD_CASE(lt, 2, 1) \
+  AP_AD_CASE(lt, 3, 0) AP_AD_CASE(lt, 3, 1) AP_AD_CASE(lt, 3, 2)
 #define AP_ALL_CASES(X) \
   X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) \
   X(2, 0) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) \
@@ -400,8 +431,8 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
 }
 
 // Gradient of phi_p with respect to A from the coupled channels of X_L.  The
-// wavefront's work units (target l, partner l, partner n range) come from a
-// schedule the library balanced over the workgroup's wavefronts.
+// wavefront's jobs (target l, component part) come from a schedule the
+// library balanced over the workgroup's wavefronts.
 template <int L>
 __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
                                         const float* Z, float* om, float* phi_p,
@@ -413,17 +444,17 @@ __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const fl
   const int u0 = uni(ptr[wave]), u1 = uni(ptr[wave + 1]);
   cptr<int32_t> units = as_const(reinterpret_cast<const int32_t*>(m.adj_units));
   for (int u = u0; u < u1; ++u) {
-    const int key = uni(units[4 * u]), np0 = uni(units[4 * u + 1]), np1 = uni(units[4 * u + 2]),
-              lt = uni(units[4 * u + 3]);
+    const int key = uni(units[4 * u]), lt = uni(units[4 * u + 3]);
     float* omt = om + t * m.apad + j * m.nlm + lt * lt;
     switch (key) {
-      AP_ALL_CASES(AP_AD_CASE)
+      AP_AD_LT(0) AP_AD_LT(1) AP_AD_LT(2) AP_AD_LT(3) AP_AD_LT(4)
       default: break;
     }
   }
 }
 #undef AP_XB_CASE
 #undef AP_AD_CASE
+#undef AP_AD_LT
 #undef AP_ALL_CASES
 
 template <int L, int RTW, int CTN>
