@@ -612,9 +612,8 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
   for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
-  // A of a tile's atoms and the gradient and phi sums of the lower ranks: the
-  // loads of the next tile are issued before the stores of the current one
-  // (registers are free there), so their latency overlaps the stores
+  // A of a tile's atoms and the gradient and phi sums of the lower ranks are
+  // loaded into registers ahead of the tile that uses them
   constexpr int kPf = (kMT * (8 * kMaxLM + 1) + kMThreads - 1) / kMThreads;
   float pa[kPf];
   float2 po[kPf];
@@ -656,13 +655,17 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     stage();
   }
   __syncthreads();
+  // ranks with spare registers fetch the next tile before this tile's work,
+  // the others just before this tile's stores
+  constexpr bool kEarly = L <= 1 || L >= 7;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int nt = min(kMT, n_items - tile * kMT);
     const int64_t base = (int64_t)tile * kMT * m.nA;
+    const int next = tile + (int)gridDim.x;
+    if (kEarly && next < n_tiles) fetch(next);
     rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
     __syncthreads();
-    const int next = tile + (int)gridDim.x;
-    if (next < n_tiles) fetch(next);
+    if (!kEarly && next < n_tiles) fetch(next);
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
       const int t = q / m.nA, e = q - t * m.nA;
       reinterpret_cast<float2*>(om_buf)[base + q] = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
