@@ -101,7 +101,10 @@ typedef struct {
 /* Full neighbour lists in slot-major ELL layout: the s-th neighbour of atom
  * i is nbr[s * n_atoms + i] (s < count[i]), sorted by ascending index;
  * rev[s * n_atoms + i] is the slot of i in the list of nbr[s * n_atoms + i].
- * nbr and rev hold capacity * n_atoms int32 each, count n_atoms. */
+ * nbr and rev hold capacity * n_atoms int32 each, count n_atoms.
+ * rev is optional (NULL): ap_build_neighbors then does not build it, and
+ * ap_ace_forces derives the reverse slots it needs (pairs whose first atom
+ * is ACE-listed) in library scratch; results are identical either way. */
 typedef struct {
   int32_t* nbr;
   int32_t* count;
@@ -155,7 +158,8 @@ typedef enum {
   AP_LAMBDA_CONST = 0,      /* lambda = value */
   AP_LAMBDA_SPHERE = 1,     /* cosine-tapered ball */
   AP_LAMBDA_HEMISPHERE = 2, /* ball centred on the first-contact surface point */
-  AP_LAMBDA_MASK = 3        /* hemisphere, raised to 1 where mask[i] != 0 */
+  AP_LAMBDA_MASK = 3,       /* hemisphere, raised to 1 where mask[i] != 0 */
+  AP_LAMBDA_GIVEN = 4       /* lambda is an input (values in [0, 1]); only the list is built */
 } ap_lambda_kind;
 
 /* Switching rule (section "Adaptive-precision potential": precise region
@@ -191,7 +195,8 @@ ap_status ap_build_neighbors(ap_ctx* ctx, const ap_systems* sys, const double* p
                              const ap_nlist* nl, int32_t* needed_capacity, void* stream);
 
 /* Switching parameter lambda[n_atoms] (ACE weight) from the rule, and the
- * ascending list of atoms with lambda > 0: ace_list[0 .. *n_ace). */
+ * ascending list of atoms with lambda > 0: ace_list[0 .. *n_ace).  With
+ * AP_LAMBDA_GIVEN, lambda is read (not written) and only the list is built. */
 ap_status ap_blend(ap_ctx* ctx, const ap_systems* sys, const double* pos,
                    const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                    int32_t* n_ace, void* stream);

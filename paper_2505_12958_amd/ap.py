@@ -177,18 +177,18 @@ def rule_struct(rule, mask_dev=None):
 class NeighbourList:
     """Caller-owned device arrays of an ap_nlist."""
 
-    def __init__(self, n_atoms, capacity=64, device="cuda"):
+    def __init__(self, n_atoms, capacity=64, device="cuda", with_rev=True):
         self.capacity = int(capacity)
         self.n_atoms = int(n_atoms)
         self.nbr = torch.empty(self.capacity * max(1, n_atoms), dtype=torch.int32, device=device)
-        self.rev = torch.empty_like(self.nbr)
+        self.rev = torch.empty_like(self.nbr) if with_rev else None
         self.count = torch.empty(max(1, n_atoms), dtype=torch.int32, device=device)
 
     def struct(self):
         s = NList()
         s.nbr = self.nbr.data_ptr()
         s.count = self.count.data_ptr()
-        s.rev = self.rev.data_ptr()
+        s.rev = self.rev.data_ptr() if self.rev is not None else None
         s.capacity = self.capacity
         return s
 
@@ -204,6 +204,8 @@ class Context:
 
     def __init__(self, eam=None, ace=None, precision=AP_PREC_FP64, device=0):
         L = lib()
+        self.has_eam = eam is not None
+        self.has_ace = ace is not None
         self._keep = []
         eam_s = None
         if eam is not None:
@@ -315,7 +317,7 @@ class Context:
 class MD:
     """Device-resident MD state (ap_md_state) for a workload."""
 
-    def __init__(self, wl, capacity=64, device="cuda"):
+    def __init__(self, wl, capacity=64, device="cuda", with_rev=False):
         N = wl.n_atoms
         f64 = dict(dtype=torch.float64, device=device)
         self.sys = SystemsArg.from_workload(wl)
@@ -328,7 +330,7 @@ class MD:
         self.fixed = torch.tensor(wl.fixed, dtype=torch.uint8, device=device)
         self.ace_list = torch.zeros(max(1, N), dtype=torch.int32, device=device)
         self.n_ace = torch.zeros(1, dtype=torch.int32, device=device)
-        self.nl = NeighbourList(N, capacity, device)
+        self.nl = NeighbourList(N, capacity, device, with_rev)
         self.virial = torch.zeros((wl.n_systems, 9), **f64)
         self.e_sys = torch.zeros(wl.n_systems, **f64)
         self.e_ind = torch.zeros(1, **f64)
@@ -359,3 +361,70 @@ class MD:
 
     def pull_indenter(self):
         self.ind_centre = np.array(self.c.ind_centre[:])
+
+
+AP_LAMBDA_GIVEN = 4
+
+
+def given_rule():
+    """ap_lambda_rule that takes lambda as an input (only the ACE list is built)."""
+    r = LambdaRule()
+    r.kind = AP_LAMBDA_GIVEN
+    return r
+
+
+class Evaluator:
+    """AP energy, forces and virial at a given (frozen) lambda through the C
+    ABI: neighbour build, list of lambda > 0, EAM, ACE, per-system sums.  The
+    device buffers are kept between calls (sized for one system layout)."""
+
+    def __init__(self, ctx, sysarg, capacity=64, device="cuda"):
+        self.ctx, self.sys = ctx, sysarg
+        N = sysarg.n_atoms
+        f64 = dict(dtype=torch.float64, device=device)
+        self.nl = NeighbourList(N, capacity, device, with_rev=False)
+        self.ace_list = torch.zeros(max(1, N), dtype=torch.int32, device=device)
+        self.n_ace = torch.zeros(1, dtype=torch.int32, device=device)
+        self.e_atom = torch.zeros(N, **f64)
+        self.e_sys = torch.zeros(sysarg.n_systems, **f64)
+        self.virial = torch.zeros((sysarg.n_systems, 9), **f64)
+        self.rule = given_rule()
+
+    def __call__(self, pos_T, lam):
+        """pos_T: (3, N) float64, lam: (N,) float64 in [0, 1] (ACE weight).
+        Returns (e_sys (n_sys,), force (3, N), virial (n_sys, 9)) as new tensors."""
+        ctx, S = self.ctx, self.sys
+        pos_T = pos_T.contiguous()
+        lam = lam.contiguous()
+        N = S.n_atoms
+        force = torch.zeros((3, N), dtype=torch.float64, device=pos_T.device)
+        ctx.build_neighbors(S, pos_T, self.nl)
+        st = lib().ap_blend(ctx.h, C.byref(S.c), _ptr(pos_T), C.byref(self.rule), _ptr(lam),
+                            _ptr(self.ace_list), _ptr(self.n_ace), _stream())
+        ctx._check(st)
+        written = False
+        if ctx.has_eam:
+            ctx.eam_forces(S, pos_T, self.nl, lam, self.e_atom, force, self.virial)
+            written = True
+        if ctx.has_ace:
+            ctx.ace_forces(S, pos_T, self.nl, lam, self.ace_list, self.n_ace, self.e_atom, force,
+                           self.virial, accumulate=written)
+        ctx.reduce_energy(S, self.e_atom, self.e_sys)
+        return self.e_sys.clone(), force, self.virial.clone()
+
+
+class APEnergy(torch.autograd.Function):
+    """Total AP energy sum_s E_s as a differentiable function of the positions
+    (lambda frozen): APEnergy.apply(pos_T, lam, evaluator) -> E.  The backward
+    pass returns -F * dL/dE; the forces come from the library's adjoint."""
+
+    @staticmethod
+    def forward(fctx, pos_T, lam, evaluator):
+        e_sys, force, _ = evaluator(pos_T.detach(), lam.detach())
+        fctx.save_for_backward(force)
+        return e_sys.sum()
+
+    @staticmethod
+    def backward(fctx, grad_e):
+        (force,) = fctx.saved_tensors
+        return -force * grad_e, None, None

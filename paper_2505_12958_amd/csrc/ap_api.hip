@@ -777,7 +777,7 @@ static ap_status upload_table(Ctx* ctx, const ap_table& t, TableDev* d, const ch
 }
 
 static ap_status check_nl(Ctx* ctx, const ap_nlist* nl) {
-  if (!nl || !nl->nbr || !nl->count || !nl->rev) return fail(ctx, AP_ERR_ARG, "neighbour list arrays missing");
+  if (!nl || !nl->nbr || !nl->count) return fail(ctx, AP_ERR_ARG, "neighbour list arrays missing");
   if (nl->capacity < 1 || nl->capacity > kMaxCap) return fail(ctx, AP_ERR_ARG, "capacity must be in [1, 256]");
   return AP_OK;
 }
@@ -851,10 +851,10 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&C.off_d, &C.H_d, &C.Hi_d, &C.ortho_d, &C.grid_d, &C.cell_base_d, &C.sys_of_d,
                     &C.chunk_lo_d, &C.chunk_hi_d, &C.sys_chunk_d})
     release(*b);
-  for (Buffer* b : {&ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
+  for (Buffer* b : {&ctx->cell_big, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
-                    &ctx->ace_rows_list, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
+                    &ctx->ace_rows_list, &ctx->rev_ace, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi})
     release(*b);
   delete ctx;
@@ -880,6 +880,7 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
   if ((st = ensure(ctx, ctx->cell_count, 4 * (size_t)nc)) ||
       (st = ensure(ctx, ctx->cell_start, 4 * (size_t)nc)) ||
       (st = ensure(ctx, ctx->cell_cursor, 4 * (size_t)nc)) ||
+      (st = ensure(ctx, ctx->cell_big, 4 * (size_t)nc)) ||
       (st = ensure(ctx, ctx->cell_of, 4 * (size_t)N)) ||
       (st = ensure(ctx, ctx->cell_atoms, 4 * (size_t)N)) ||
       (st = ensure(ctx, ctx->cell_pos, 32 * (size_t)N)) ||
@@ -896,10 +897,11 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
                         hipMemcpyDeviceToDevice, s));
   AP_HIP(launch_scatter(sv, pos, (const int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_cursor.p,
                         (int32_t*)ctx->cell_atoms.p, (double4*)ctx->cell_pos.p, s));
-  AP_HIP(launch_fill_nbr(sv, pos, (const int32_t*)ctx->cell_of.p, (const int32_t*)ctx->cell_start.p,
-                         (const int32_t*)ctx->cell_count.p, (const double4*)ctx->cell_pos.p, nl->nbr,
-                         nl->count, nl->capacity, flags, s));
-  AP_HIP(launch_rev((int32_t)N, nl->nbr, nl->count, nl->rev, s));
+  AP_HIP(launch_fill_nbr_cells(sv, nc, pos, (const int32_t*)ctx->cell_of.p,
+                               (const int32_t*)ctx->cell_start.p, (const int32_t*)ctx->cell_count.p,
+                               (const double4*)ctx->cell_pos.p, nl->nbr, nl->count, nl->capacity,
+                               flags, (int32_t*)ctx->cell_big.p, s));
+  if (nl->rev) AP_HIP(launch_rev((int32_t)N, nl->nbr, nl->count, nl->rev, s));
   if (needed_capacity) {
     int32_t need = 0;
     AP_HIP(hipMemcpyAsync(&need, flags, 4, hipMemcpyDeviceToHost, s));
@@ -919,10 +921,11 @@ ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap
   if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
   hipStream_t s = (hipStream_t)stream;
   if (!rule || !lambda || !ace_list || !n_ace) return fail(ctx, AP_ERR_ARG, "blend arguments missing");
-  if (rule->kind < AP_LAMBDA_CONST || rule->kind > AP_LAMBDA_MASK) return fail(ctx, AP_ERR_ARG, "bad rule kind");
+  if (rule->kind < AP_LAMBDA_CONST || rule->kind > AP_LAMBDA_GIVEN) return fail(ctx, AP_ERR_ARG, "bad rule kind");
   if (rule->kind == AP_LAMBDA_CONST && !(rule->value >= 0.0 && rule->value <= 1.0))
     return fail(ctx, AP_ERR_ARG, "constant lambda must be in [0, 1]");
-  if (rule->kind != AP_LAMBDA_CONST && (!(rule->r_full >= 0) || !(rule->taper > 0)))
+  if (rule->kind != AP_LAMBDA_CONST && rule->kind != AP_LAMBDA_GIVEN &&
+      (!(rule->r_full >= 0) || !(rule->taper > 0)))
     return fail(ctx, AP_ERR_ARG, "rule needs r_full >= 0 and taper > 0");
   if (rule->kind == AP_LAMBDA_MASK && !rule->mask) return fail(ctx, AP_ERR_ARG, "mask rule needs a mask");
   ap_status st;
@@ -1030,7 +1033,14 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   }
   {
     PhaseTimer timer(ctx, AP_PHASE_ACE_GATHER, s);
-    AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, nl->rev, nl->capacity,
+    const int32_t* rev = nl->rev;
+    if (!rev) {
+      // no full reverse index: the slots of the pairs that start at a listed atom
+      if ((st = ensure(ctx, ctx->rev_ace, 4 * (size_t)nl->capacity * std::max<int64_t>(N, 1)))) return st;
+      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, (int32_t*)ctx->rev_ace.p, s));
+      rev = (const int32_t*)ctx->rev_ace.p;
+    }
+    AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev, nl->capacity,
                              (const int32_t*)ctx->ace_row.p, ctx->pair_g.p, force, acc, s));
   }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;

@@ -153,10 +153,11 @@ struct Ctx {
   std::vector<Buffer> owned;            // model tables
   SysCache sys;
   // scratch, grown on demand
+  Buffer cell_big;
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
-  Buffer ace_row, pair_g, ace_counter, ace_rows_list;
+  Buffer ace_row, pair_g, ace_counter, ace_rows_list, rev_ace;
   Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
@@ -208,6 +209,11 @@ hipError_t launch_scan_exclusive(const int32_t* in, int32_t* out, int32_t n, int
                                  hipStream_t s);
 hipError_t launch_scatter(const SysView& sv, const double* pos, const int32_t* cell_of,
                           int32_t* cursor, int32_t* cell_atoms, double4* cell_pos, hipStream_t s);
+hipError_t launch_fill_nbr_cells(const SysView& sv, int32_t n_cells, const double* pos,
+                                 const int32_t* cell_of, const int32_t* cell_start,
+                                 const int32_t* cell_count, const double4* cell_pos, int32_t* nbr,
+                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_cells,
+                                 hipStream_t s);
 hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* cell_of,
                            const int32_t* cell_start, const int32_t* cell_count,
                            const double4* cell_pos, int32_t* nbr, int32_t* count, int32_t cap,
@@ -254,6 +260,8 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             double* e_atom, double* vir_atom, hipStream_t s, int phase);
 size_t ace_mixed_lds_bytes(const MixDev& m);
+hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
                              const void* pair_g, double* force, bool accumulate, hipStream_t s);

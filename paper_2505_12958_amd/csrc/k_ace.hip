@@ -253,6 +253,42 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   return hipGetLastError();
 }
 
+// Reverse slots of the pairs that start at an ACE-listed atom only: for
+// listed atom j and slot r (k = nbr[r][j]), rev[s][k] = r where s is the slot
+// of j in the (ascending) list of k.  Entries of pairs whose first atom is
+// not listed are left untouched (the gather never reads them).  One
+// wavefront per listed atom, one lane per slot.
+__global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+                          const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
+                          int32_t* __restrict__ rev) {
+  const int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int m = ace_list ? *n_ace : n;
+  if (item >= m) return;
+  const int j = ace_list ? ace_list[item] : item;
+  const int cj = count[j];
+  for (int r = lane; r < cj; r += 64) {
+    const int k = nbr[(int64_t)r * n + j];
+    int lo = 0, hi = count[k] - 1, pos = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int v = nbr[(int64_t)mid * n + k];
+      if (v == j) { pos = mid; break; }
+      if (v < j) lo = mid + 1; else hi = mid - 1;
+    }
+    if (pos >= 0) rev[(int64_t)pos * n + k] = r;
+  }
+}
+
+hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  const int64_t threads = (int64_t)n_atoms * 64;
+  hipLaunchKernelGGL(k_rev_ace, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
+                     nbr, count, ace_list, n_ace, rev);
+  return hipGetLastError();
+}
+
 // F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only
 template <typename G>
 __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,

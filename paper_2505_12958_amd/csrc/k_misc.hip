@@ -141,7 +141,9 @@ __global__ void k_blend(int n, const double* __restrict__ pos, ap_lambda_rule ru
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double lam;
-  if (rule.kind == AP_LAMBDA_CONST) {
+  if (rule.kind == AP_LAMBDA_GIVEN) {
+    lam = lambda[i];
+  } else if (rule.kind == AP_LAMBDA_CONST) {
     lam = rule.value;
   } else {
     const double x = pos[i] - rule.centre[0];
@@ -158,7 +160,7 @@ __global__ void k_blend(int n, const double* __restrict__ pos, ap_lambda_rule ru
     if (rule.kind == AP_LAMBDA_MASK && rule.mask[i]) lam = 1.0;
     if (geo == 0.0 && pos[2 * n + i] >= rule.z_surface_min) lam = 0.0;
   }
-  lambda[i] = lam;
+  if (rule.kind != AP_LAMBDA_GIVEN) lambda[i] = lam;
   flag[i] = lam > 0.0 ? 1 : 0;
 }
 

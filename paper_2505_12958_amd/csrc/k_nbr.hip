@@ -101,22 +101,20 @@ hipError_t launch_scatter(const SysView& sv, const double* pos, const int32_t* c
 constexpr int kWavesPerBlock = 4;
 constexpr int kListLds = kMaxCap;
 
-__global__ __launch_bounds__(256) void k_fill_nbr(SysView sv, const double* __restrict__ pos,
-                                                  const int32_t* __restrict__ cell_of,
-                                                  const int32_t* __restrict__ cell_start,
-                                                  const int32_t* __restrict__ cell_count,
-                                                  const double4* __restrict__ cell_pos,
-                                                  int32_t* __restrict__ nbr,
-                                                  int32_t* __restrict__ count, int cap,
-                                                  int32_t* __restrict__ overflow) {
-  __shared__ int list[kWavesPerBlock][kListLds];
-  __shared__ int st_cell[kWavesPerBlock][32];
-  __shared__ int st_pre[kWavesPerBlock][33];
+__device__ __forceinline__ void atom_list_direct(const SysView& sv, const double* __restrict__ pos,
+                                                 const int32_t* __restrict__ cell_of,
+                                                 const int32_t* __restrict__ cell_start,
+                                                 const int32_t* __restrict__ cell_count,
+                                                 const double4* __restrict__ cell_pos,
+                                                 int32_t* __restrict__ nbr,
+                                                 int32_t* __restrict__ count, int cap,
+                                                 int32_t* __restrict__ overflow, int i,
+                                                 int (&list)[kWavesPerBlock][kListLds],
+                                                 int (&st_cell)[kWavesPerBlock][32],
+                                                 int (&st_pre)[kWavesPerBlock][33]) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int n = sv.n_atoms;
-  const int i = blockIdx.x * kWavesPerBlock + w;
-  if (i >= n) return;  // whole wavefront leaves together
   const int s = sv.sys_of[i];
   const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
   const int* g = sv.grid + 3 * s;
@@ -198,6 +196,42 @@ __global__ __launch_bounds__(256) void k_fill_nbr(SysView sv, const double* __re
   if (lane == 0) count[i] = cnt < cap ? cnt : cap;
 }
 
+__global__ __launch_bounds__(256) void k_fill_nbr(SysView sv, const double* __restrict__ pos,
+                                                  const int32_t* __restrict__ cell_of,
+                                                  const int32_t* __restrict__ cell_start,
+                                                  const int32_t* __restrict__ cell_count,
+                                                  const double4* __restrict__ cell_pos,
+                                                  int32_t* __restrict__ nbr,
+                                                  int32_t* __restrict__ count, int cap,
+                                                  int32_t* __restrict__ overflow) {
+  __shared__ int list[kWavesPerBlock][kListLds];
+  __shared__ int st_cell[kWavesPerBlock][32];
+  __shared__ int st_pre[kWavesPerBlock][33];
+  const int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (i >= sv.n_atoms) return;  // whole wavefront leaves together
+  atom_list_direct(sv, pos, cell_of, cell_start, cell_count, cell_pos, nbr, count, cap, overflow, i,
+                   list, st_cell, st_pre);
+}
+
+__global__ __launch_bounds__(256) void k_fill_nbr_big(SysView sv, const double* __restrict__ pos,
+                                                      const int32_t* __restrict__ cell_of,
+                                                      const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ cell_count,
+                                                      const double4* __restrict__ cell_pos,
+                                                      int32_t* __restrict__ nbr,
+                                                      int32_t* __restrict__ count, int cap,
+                                                      int32_t* __restrict__ overflow,
+                                                      const int32_t* __restrict__ big_cells) {
+  __shared__ int list[kWavesPerBlock][kListLds];
+  __shared__ int st_cell[kWavesPerBlock][32];
+  __shared__ int st_pre[kWavesPerBlock][33];
+  const int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (i >= sv.n_atoms) return;  // whole wavefront leaves together
+  if (big_cells[cell_of[i]] == 0) return;
+  atom_list_direct(sv, pos, cell_of, cell_start, cell_count, cell_pos, nbr, count, cap, overflow, i,
+                   list, st_cell, st_pre);
+}
+
 hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* cell_of,
                            const int32_t* cell_start, const int32_t* cell_count,
                            const double4* cell_pos, int32_t* nbr, int32_t* count, int32_t cap,
@@ -206,6 +240,162 @@ hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* 
   const int blocks = (sv.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
   hipLaunchKernelGGL(k_fill_nbr, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, sv, pos, cell_of,
                      cell_start, cell_count, cell_pos, nbr, count, cap, overflow);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// One workgroup per cell.  The candidates of the cell's stencil (at most 27
+// deduplicated cells) are gathered into LDS once and sorted by atom index
+// (bitonic); each atom of the cell then filters the sorted candidates with
+// the canonical FP64 test, so its accepted neighbours come out in ascending
+// order and are stored directly (ballot compaction keeps the order).  A cell
+// whose stencil holds more than kMaxCand candidates falls back to the
+// wave-per-atom kernel above for its atoms.
+constexpr int kCellThreads = 256;
+constexpr int kMaxCand = 1024;
+
+__global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
+    SysView sv, const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
+    const double4* __restrict__ cell_pos, int32_t* __restrict__ nbr, int32_t* __restrict__ count,
+    int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_cells) {
+  __shared__ long long key[kMaxCand];  // (atom index << 16) | candidate position
+  __shared__ double4 cpos[kMaxCand];
+  __shared__ int st_cell[32];
+  __shared__ int st_pre[33];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = blockIdx.x;
+  const int n_here = cell_count[c];
+  if (n_here == 0) return;  // whole workgroup
+  // system of this cell
+  int lo = 0, hi = sv.n_sys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sv.cell_base[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int s = lo;
+  const int* g = sv.grid + 3 * s;
+  const int ci = c - sv.cell_base[s];
+  const int cc[3] = {ci / (g[1] * g[2]), (ci / g[2]) % g[1], ci % g[2]};
+  if (wave == 0) {
+    int my_cell = -1, my_cnt = 0;
+    if (lane < 27) {
+      const int idx[3] = {lane / 9, (lane / 3) % 3, lane % 3};
+      int co[3];
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        const int gk = g[k];
+        if (sv.per[k] && gk < 3) {
+          if (idx[k] >= gk) ok = false;
+          co[k] = idx[k];
+        } else {
+          int v = cc[k] + idx[k] - 1;
+          if (sv.per[k]) {
+            v = v < 0 ? v + gk : (v >= gk ? v - gk : v);
+          } else if (v < 0 || v >= gk) {
+            ok = false;
+          }
+          co[k] = v;
+        }
+      }
+      if (ok) {
+        my_cell = sv.cell_base[s] + (co[0] * g[1] + co[1]) * g[2] + co[2];
+        my_cnt = cell_count[my_cell];
+      }
+    }
+    const int incl = wave_incl_scan_i32(my_cnt, lane);
+    if (lane < 27) {
+      st_cell[lane] = my_cell;
+      st_pre[lane] = incl - my_cnt;
+    }
+    if (lane == 26) st_pre[27] = incl;
+  }
+  __syncthreads();
+  const int total = st_pre[27];
+  const int n = sv.n_atoms;
+  const int first = cell_start[c];
+  if (total > kMaxCand) {
+    if (tid == 0) big_cells[c] = 1;
+    return;
+  }
+  int P = 64;
+  while (P < total) P <<= 1;
+  for (int q = tid; q < P; q += kCellThreads) {
+    if (q < total) {
+      int k = 0;
+      while (k < 26 && st_pre[k + 1] <= q) ++k;
+      const double4 v = cell_pos[cell_start[st_cell[k]] + (q - st_pre[k])];
+      cpos[q] = v;
+      key[q] = ((long long)(int)v.w << 16) | q;
+    } else {
+      key[q] = 0x7fffffffffffffffll;
+    }
+  }
+  __syncthreads();
+  // bitonic sort of the keys (ascending atom index)
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = tid; t < P; t += kCellThreads) {
+        const int u = t ^ jj;
+        if (u > t) {
+          const long long a = key[t], b = key[u];
+          if ((a > b) == ((t & k) == 0)) {
+            key[t] = b;
+            key[u] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const bool ortho = sv.ortho[s] != 0;
+  const double* H = sv.H + 9 * s;
+  const double* Hi = sv.Hi + 9 * s;
+  for (int a = wave; a < n_here; a += kCellThreads / 64) {
+    const double4 pi = cell_pos[first + a];
+    const int i = (int)pi.w;
+    int cnt = 0;
+    for (int base = 0; base < total; base += 64) {
+      const int q = base + lane;
+      bool acc = false;
+      int j = -1;
+      if (q < total) {
+        const long long kv = key[q];
+        j = (int)(kv >> 16);
+        if (j != i) {
+          const double4 pj = cpos[(int)(kv & 0xffff)];
+          double dx, dy, dz;
+          displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+          acc = norm2(dx, dy, dz) < sv.rc2;
+        }
+      }
+      const unsigned long long b = __ballot(acc);
+      if (acc) {
+        const int p = cnt + __popcll(b & ((1ull << lane) - 1ull));
+        if (p < cap) nbr[(int64_t)p * n + i] = j;
+      }
+      cnt += __popcll(b);
+    }
+    if (lane == 0) {
+      count[i] = cnt < cap ? cnt : cap;
+      if (cnt > cap) atomicMax(overflow, cnt);
+    }
+  }
+}
+
+hipError_t launch_fill_nbr_cells(const SysView& sv, int32_t n_cells, const double* pos,
+                                 const int32_t* cell_of, const int32_t* cell_start,
+                                 const int32_t* cell_count, const double4* cell_pos, int32_t* nbr,
+                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_cells,
+                                 hipStream_t s) {
+  if (sv.n_atoms == 0 || n_cells == 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(big_cells, 0, n_cells, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_nbr_cell, dim3(n_cells), dim3(kCellThreads), 0, s, sv, cell_start,
+                     cell_count, cell_pos, nbr, count, cap, overflow, big_cells);
+  const int blocks = (sv.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL(k_fill_nbr_big, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, sv, pos, cell_of,
+                     cell_start, cell_count, cell_pos, nbr, count, cap, overflow, big_cells);
   return hipGetLastError();
 }
 

@@ -6,7 +6,7 @@ from paper_2505_12958_amd import ap
 
 
 def run_force(wl, precision=ap.AP_PREC_FP64, capacity=64, lam=None, with_eam=True, with_ace=True,
-              virial=True, pos=None):
+              virial=True, pos=None, with_rev=True):
     """One AP force evaluation on the GPU: blend (unless lam given), neighbours,
     EAM, ACE.  Returns host numpy arrays."""
     dev = "cuda"
@@ -15,7 +15,7 @@ def run_force(wl, precision=ap.AP_PREC_FP64, capacity=64, lam=None, with_eam=Tru
     p = wl.pos if pos is None else pos
     P = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float64, device=dev)
     ctx = ap.Context(wl.eam if with_eam else None, wl.ace if with_ace else None, precision)
-    nl = ap.NeighbourList(N, capacity, dev)
+    nl = ap.NeighbourList(N, capacity, dev, with_rev)
     ctx.build_neighbors(S, P, nl)
     lam_t = torch.zeros(N, dtype=torch.float64, device=dev)
     ace_list = torch.zeros(max(1, N), dtype=torch.int32, device=dev)
@@ -47,6 +47,10 @@ def run_force(wl, precision=ap.AP_PREC_FP64, capacity=64, lam=None, with_eam=Tru
                e_sys=e_sys.cpu().numpy(), lam=lam_t.cpu().numpy(),
                ace_list=ace_list.cpu().numpy()[:na], nl=nl.rows(),
                count=nl.count.cpu().numpy()[:N])
+    if with_rev:
+        cnt = out["count"]
+        rv = nl.rev.cpu().numpy().reshape(capacity, -1)[:, :N]
+        out["rev"] = [rv[: cnt[i], i].copy() for i in range(N)]
     if virial:
         out["virial"] = W.cpu().numpy().reshape(-1, 3, 3)
     ctx.close()

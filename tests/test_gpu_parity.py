@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import run_force
+from paper_2505_12958_amd import ap
 from oracle.ap import APOracle
 from oracle.geometry import Systems
 from oracle.switching import ace_list as o_ace_list
@@ -52,6 +53,31 @@ def test_neighbour_lists_bit_exact(name):
     assert len(g["nl"]) == wl.n_atoms
     for i in range(wl.n_atoms):
         assert np.array_equal(g["nl"][i], ref["nl"][i][0]), i
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_reverse_slots(name):
+    """rev[s][i] is the slot of i in the list of j = nbr[s][i]."""
+    wl, ref = oracle(name)
+    g = run_force(wl, with_ace=False)
+    for i in range(wl.n_atoms):
+        js, rv = g["nl"][i], g["rev"][i]
+        for j, r in zip(js, rv):
+            assert g["nl"][j][r] == i, (i, j, r)
+
+
+@pytest.mark.parametrize("precision", [ap.AP_PREC_FP64, ap.AP_PREC_MIXED])
+def test_forces_without_full_reverse_index(precision):
+    """ACE forces from lists built without rev (reverse slots derived for the
+    ACE pairs only) equal those with the full index, bit for bit."""
+    wl, _ = oracle("wslab10")
+    a = run_force(wl, precision=precision, with_rev=True)
+    b = run_force(wl, precision=precision, with_rev=False)
+    assert np.array_equal(a["forces"], b["forces"]) or precision == ap.AP_PREC_MIXED
+    if precision == ap.AP_PREC_MIXED:
+        scale = np.linalg.norm(a["forces"])
+        assert np.linalg.norm(a["forces"] - b["forces"]) / scale <= 1e-6
+    assert np.array_equal(a["e_atom"], b["e_atom"]) or precision == ap.AP_PREC_MIXED
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -1,0 +1,44 @@
+"""200 velocity-Verlet steps of the 108,000-atom Cu-like indentation slab
+(moving indenter) on the FP64 path; at steps 0, 50, 100, 150 and 200 the
+mixed path evaluated at the same positions (and indenter position) stays
+within 1e-5 relative force error, and the FP64 trajectory stays finite."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2505_12958_amd import ap
+from paper_2505_12958_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fp64_trajectory_mixed_forces_along_it():
+    wl = w.workload(2)
+    c64 = ap.Context(wl.eam, wl.ace, ap.AP_PREC_FP64)
+    cmx = ap.Context(wl.eam, wl.ace, ap.AP_PREC_MIXED)
+    # the random ACE region is only weakly bound and compresses under the tip:
+    # capacity 96 instead of the default 64
+    st = ap.MD(wl, capacity=96)
+    probe = ap.MD(wl, capacity=96)
+    c64.step(st.sys, st, 0)
+    errs = []
+    for step in range(0, 201, 50):
+        if step > 0:
+            c64.step(st.sys, st, 50)
+        torch.cuda.synchronize()
+        c64.check()
+        probe.pos.copy_(st.pos)
+        for k in range(3):
+            probe.c.ind_centre[k] = st.c.ind_centre[k]
+        cmx.step(probe.sys, probe, 0)
+        torch.cuda.synchronize()
+        e = float(torch.linalg.norm(probe.force - st.force) / torch.linalg.norm(st.force))
+        errs.append(e)
+        print(f"step {step}: n_ace {int(st.n_ace.item())}, max|F| {float(st.force.abs().max()):.3f}, "
+              f"mixed force rel err {e:.2e}, indenter z {st.c.ind_centre[2]:.4f}")
+    assert all(np.isfinite(errs)) and max(errs) <= 1e-5
+    # the indenter moved by 200 dt v
+    z0 = float(wl.indenter["centre"][2])
+    assert abs((z0 - st.c.ind_centre[2]) - 200 * wl.dt * float(-wl.indenter["vel"][2])) < 1e-9
+    c64.close()
+    cmx.close()
