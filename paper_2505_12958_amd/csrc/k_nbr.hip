@@ -245,21 +245,22 @@ hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* 
 
 // --------------------------------------------------------------------------
 // One workgroup per cell.  The candidates of the cell's stencil (at most 27
-// deduplicated cells) are gathered into LDS once and sorted by atom index
-// (bitonic); each atom of the cell then filters the sorted candidates with
-// the canonical FP64 test, so its accepted neighbours come out in ascending
-// order and are stored directly (ballot compaction keeps the order).  A cell
-// whose stencil holds more than kMaxCand candidates falls back to the
-// wave-per-atom kernel above for its atoms.
+// deduplicated cells) are gathered into LDS once and shared by the cell's
+// atoms, one wavefront per atom: lanes test 64 candidates at a time with the
+// canonical FP64 rule, accepted indices are compacted into a per-wavefront
+// LDS list with a ballot, then each lane ranks its entries (indices are
+// unique) and stores them in ascending order.  A cell whose stencil holds
+// more than kMaxCand candidates falls back to the kernel above for its atoms.
 constexpr int kCellThreads = 256;
+constexpr int kCellWaves = kCellThreads / 64;
 constexpr int kMaxCand = 1024;
 
 __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     SysView sv, const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
     const double4* __restrict__ cell_pos, int32_t* __restrict__ nbr, int32_t* __restrict__ count,
     int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_cells) {
-  __shared__ long long key[kMaxCand];  // (atom index << 16) | candidate position
   __shared__ double4 cpos[kMaxCand];
+  __shared__ int list[kCellWaves][kListLds];
   __shared__ int st_cell[32];
   __shared__ int st_pre[33];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -318,40 +319,19 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     if (tid == 0) big_cells[c] = 1;
     return;
   }
-  int P = 64;
-  while (P < total) P <<= 1;
-  for (int q = tid; q < P; q += kCellThreads) {
-    if (q < total) {
-      int k = 0;
-      while (k < 26 && st_pre[k + 1] <= q) ++k;
-      const double4 v = cell_pos[cell_start[st_cell[k]] + (q - st_pre[k])];
-      cpos[q] = v;
-      key[q] = ((long long)(int)v.w << 16) | q;
-    } else {
-      key[q] = 0x7fffffffffffffffll;
-    }
+  // candidates of the stencil, cell after cell
+  for (int k = 0; k < 27; ++k) {
+    const int cnt_k = st_pre[k + 1] - st_pre[k];
+    if (cnt_k == 0) continue;
+    const int src = cell_start[st_cell[k]], dst = st_pre[k];
+    for (int q = tid; q < cnt_k; q += kCellThreads) cpos[dst + q] = cell_pos[src + q];
   }
   __syncthreads();
-  // bitonic sort of the keys (ascending atom index)
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = tid; t < P; t += kCellThreads) {
-        const int u = t ^ jj;
-        if (u > t) {
-          const long long a = key[t], b = key[u];
-          if ((a > b) == ((t & k) == 0)) {
-            key[t] = b;
-            key[u] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
-  for (int a = wave; a < n_here; a += kCellThreads / 64) {
+  int* lw = list[wave];
+  for (int a = wave; a < n_here; a += kCellWaves) {
     const double4 pi = cell_pos[first + a];
     const int i = (int)pi.w;
     int cnt = 0;
@@ -360,10 +340,9 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
       bool acc = false;
       int j = -1;
       if (q < total) {
-        const long long kv = key[q];
-        j = (int)(kv >> 16);
+        const double4 pj = cpos[q];
+        j = (int)pj.w;
         if (j != i) {
-          const double4 pj = cpos[(int)(kv & 0xffff)];
           double dx, dy, dz;
           displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
           acc = norm2(dx, dy, dz) < sv.rc2;
@@ -372,14 +351,23 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
       const unsigned long long b = __ballot(acc);
       if (acc) {
         const int p = cnt + __popcll(b & ((1ull << lane) - 1ull));
-        if (p < cap) nbr[(int64_t)p * n + i] = j;
+        if (p < kListLds) lw[p] = j;
       }
       cnt += __popcll(b);
+    }
+    __syncwarp_ap();
+    const int m = cnt < kListLds ? cnt : kListLds;
+    for (int e = lane; e < m; e += 64) {
+      const int v = lw[e];
+      int rank = 0;
+      for (int q = 0; q < m; ++q) rank += lw[q] < v;
+      if (rank < cap) nbr[(int64_t)rank * n + i] = v;
     }
     if (lane == 0) {
       count[i] = cnt < cap ? cnt : cap;
       if (cnt > cap) atomicMax(overflow, cnt);
     }
+    __syncwarp_ap();
   }
 }
 
