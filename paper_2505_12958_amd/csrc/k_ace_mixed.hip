@@ -517,6 +517,11 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
 // ---- kernel 1: bond basis and atomic basis A, one wavefront per ACE atom
 constexpr int kBasisWaves = 4;
 
+// NM, LM, KK > 0: model shape fixed at compile time (n_max, l_max, K), so
+// every loop over radial and angular indices unrolls with constant trip
+// counts and the radial weights are read as scalar loads at constant
+// offsets; NM = 0: the shape is read from the model at run time.
+template <int NM, int LM, int KK>
 __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
     SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ count, const int32_t* __restrict__ ace_list,
@@ -524,7 +529,9 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int stride = m.nnl + m.nlm;
+  const int n_max = NM ? NM : m.n_max, l_max = NM ? LM : m.l_max, K = NM ? KK : m.K;
+  const int lp1 = l_max + 1, nlm = lp1 * lp1, nnl = n_max * lp1, nA = n_max * nlm;
+  const int stride = nnl + nlm;
   float* RY = reinterpret_cast<float*>(lds) + wave * 64 * stride;
   const int n = sv.n_atoms;
   const int n_items = ace_list ? *n_ace_p : n_all;
@@ -533,7 +540,6 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   const int a = ace_list ? ace_list[item] : item;
   const int c = count[a];
   const int sy = sv.sys_of[a];
-  const int lp1 = m.l_max + 1;
   const float rc = (float)m.rc;
   float acc[(kMaxN * kMaxLM + 63) / 64];
 #pragma unroll
@@ -549,20 +555,22 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
       const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
       const float r = sqrtf(fx * fx + fy * fy + fz * fz);
       float g[kMaxK], dg[kMaxK];
-      cheb_basis<float>(m.K, rc, r, g, dg);
-      for (int nl = 0; nl < m.nnl; ++nl) {
+      cheb_basis<float>(K, rc, r, g, dg);
+#pragma unroll
+      for (int nl = 0; nl < (NM ? NM * (LM + 1) : kMaxN * (kMaxL + 1)); ++nl) {
+        if (nl >= nnl) break;
         float v = 0.f;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k)
-          if (k < m.K) v += m.Wf[nl * m.K + k] * g[k];
+          if (k < K) v += m.Wf[nl * K + k] * g[k];
         o[nl] = v;
       }
       float Y[kMaxLM];
       const float ir = 1.f / r;
-      real_ylm<float>(m.l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, Y, nullptr);
+      real_ylm<float>(l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, Y, nullptr);
 #pragma unroll
       for (int q = 0; q < kMaxLM; ++q)
-        if (q < m.nlm) o[m.nnl + q] = Y[q];
+        if (q < nlm) o[nnl + q] = Y[q];
     } else {
       for (int q = 0; q < stride; ++q) o[q] = 0.f;
     }
@@ -571,12 +579,15 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 #pragma unroll
     for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
       const int e = lane + 64 * r;
-      if (e >= m.nA) break;
-      const int nn = e / m.nlm, lm = e % m.nlm;
+      if (e >= nA) break;
+      const int nn = e / nlm, lm = e % nlm;
       int l = 0;
       while ((l + 1) * (l + 1) <= lm) ++l;
       float v = 0.f;
-      for (int s2 = 0; s2 < nb; ++s2) v += RY[s2 * stride + nn * lp1 + l] * RY[s2 * stride + m.nnl + lm];
+      const float* ra = RY + nn * lp1 + l;
+      const float* ya = RY + nnl + lm;
+#pragma unroll 4
+      for (int s2 = 0; s2 < nb; ++s2) v += ra[s2 * stride] * ya[s2 * stride];
       acc[r] += v;
     }
     __syncwarp_ap();
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 #pragma unroll
   for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
     const int e = lane + 64 * r;
-    if (e < m.nA) A_out[(int64_t)item * m.nA + e] = acc[r];
+    if (e < nA) A_out[(int64_t)item * nA + e] = acc[r];
   }
 }
 
@@ -678,6 +689,7 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
 }
 
 // ---- kernel 3: embedding (FP64), bond gradients and virial, one wavefront per atom
+template <int NM, int LM, int KK>
 __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
@@ -720,7 +732,8 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
   __syncwarp_ap();
   const int c = count[a];
   const int sy = sv.sys_of[a];
-  const int lp1 = m.l_max + 1;
+  const int n_max = NM ? NM : m.n_max, l_max = NM ? LM : m.l_max, K = NM ? KK : m.K;
+  const int lp1 = l_max + 1, nlm = lp1 * lp1;
   const float rc = (float)m.rc;
   double w9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int s = lane; s < c; s += 64) {
@@ -732,20 +745,22 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     const float r = sqrtf(fx * fx + fy * fy + fz * fz);
     const float ir = 1.f / r;
     float g[kMaxK], dg[kMaxK];
-    cheb_basis<float>(m.K, rc, r, g, dg);
+    cheb_basis<float>(K, rc, r, g, dg);
     float ca[kMaxLM], cb[kMaxLM];
 #pragma unroll
     for (int q = 0; q < kMaxLM; ++q) { ca[q] = 0.f; cb[q] = 0.f; }
-    for (int nn = 0; nn < m.n_max; ++nn) {
+#pragma unroll
+    for (int nn = 0; nn < (NM ? NM : kMaxN); ++nn) {
+      if (nn >= n_max) break;
 #pragma unroll
       for (int l = 0; l <= kMaxL; ++l) {
-        if (l > m.l_max) break;
+        if (l > l_max) break;
         float R = 0.f, dR = 0.f;
-        const float* Wr = m.Wf + (nn * lp1 + l) * m.K;
+        const float* Wr = m.Wf + (nn * lp1 + l) * K;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k)
-          if (k < m.K) { R += Wr[k] * g[k]; dR += Wr[k] * dg[k]; }
-        const float* omn = om + nn * m.nlm;
+          if (k < K) { R += Wr[k] * g[k]; dR += Wr[k] * dg[k]; }
+        const float* omn = om + nn * nlm;
 #pragma unroll
         for (int q = l * l; q < (l + 1) * (l + 1); ++q) {
           ca[q] += omn[q] * R;
@@ -754,7 +769,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
       }
     }
     float rad, gx, gy, gz;
-    ylm_contract<float>(m.l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, ca, cb, rad, gx, gy, gz);
+    ylm_contract<float>(l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, ca, cb, rad, gx, gy, gz);
     gx += rad * fx * ir;
     gy += rad * fy * ir;
     gz += rad * fz * ir;
@@ -786,8 +801,13 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
   if (phase == 0) {
     if (n_atoms == 0) return hipSuccess;
     const size_t lds = (size_t)kBasisWaves * 64 * (m.nnl + m.nlm) * 4;
-    hipLaunchKernelGGL(k_ace_basis, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr,
-                       count, ace_list, n_ace, n_atoms, A_buf);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr, count,
+                         ace_list, n_ace, n_atoms, A_buf);
+    };
+    if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_basis<8, 4, 8>);
+    else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_basis<6, 3, 6>);
+    else go(k_ace_basis<0, 0, 0>);
   } else if (phase == 1) {
     int dev = 0, n_cu = 256;
     hipGetDevice(&dev);
@@ -819,9 +839,14 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
   } else {
     if (n_atoms == 0) return hipSuccess;
     const size_t lds = (size_t)kBasisWaves * m.apad * 4;
-    hipLaunchKernelGGL(k_ace_grad, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr,
-                       count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf, pair_g,
-                       e_atom, vir_atom);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr, count,
+                         cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf, pair_g,
+                         e_atom, vir_atom);
+    };
+    if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_grad<8, 4, 8>);
+    else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_grad<6, 3, 6>);
+    else go(k_ace_grad<0, 0, 0>);
   }
   return hipGetLastError();
 }

@@ -253,7 +253,7 @@ hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* 
 // more than kMaxCand candidates falls back to the kernel above for its atoms.
 constexpr int kCellThreads = 256;
 constexpr int kCellWaves = kCellThreads / 64;
-constexpr int kMaxCand = 1024;
+constexpr int kMaxCand = 512;
 
 __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     SysView sv, const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
