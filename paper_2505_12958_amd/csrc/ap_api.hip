@@ -509,6 +509,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   std::vector<uint4> ctile;
   std::map<std::tuple<int, int, int>, int> pat_id;
   size_t big = (size_t)4 * 64 * (a.nnl + nlm) * 4;
+  std::vector<size_t> xbytes(Lmax + 1, 0), zbytes(Lmax + 1, 0);
   auto bf16_rne = [](float f) -> uint16_t {
     uint32_t u;
     memcpy(&u, &f, 4);
@@ -572,8 +573,10 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     P.zstr = 8 * w + 1;
     if ((P.nrow16 / 16 + kMixWaves - 1) / kMixWaves > kMixRtw[L] || P.ct != L + 1 || nmax > 8)
       return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model outside the mixed kernels' tiling (n_max <= 8, rows per rank)");
-    big = std::max(big, (size_t)P.ct * 16 * P.kstr * 2 * 2);
-    big = std::max(big, (size_t)P.nrow * P.zstr * 4);
+    xbytes[L] = ((size_t)P.ct * 16 * P.kstr * 2 * 2 + 15) / 16 * 16;
+    zbytes[L] = (size_t)P.nrow * P.zstr * 4;
+    big = std::max(big, xbytes[L]);
+    big = std::max(big, zbytes[L]);
     // dense folded matrix of this L (both sets)
     std::vector<double> D((size_t)P.nrow * P.nrow * 2, 0.0);
     for (auto& kv : Cm[L]) {
@@ -743,6 +746,13 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   size_t tab = (size_t)nidx * nidx * 4;
   for (int L = 0; L <= Lmax; ++L) tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16);
   x.big_off = (int32_t)((x.tab_off + tab + 15) / 16 * 16);
+  // ranks whose X_L and Z_L fit in LDS together keep X_L for both sets
+  for (int L = 0; L <= Lmax; ++L) {
+    MixL& P = x.lv[L];
+    P.xonce = (size_t)x.big_off + xbytes[L] + zbytes[L] + 1024 <= 160 * 1024 ? 1 : 0;
+    P.zoff = P.xonce ? (int32_t)xbytes[L] : 0;
+    if (P.xonce) big = std::max(big, xbytes[L] + zbytes[L]);
+  }
   x.big_bytes = (int32_t)big;
   if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
     return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");

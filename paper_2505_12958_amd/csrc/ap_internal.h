@@ -101,6 +101,8 @@ struct MixL {
   int32_t kstr, zstr;               // LDS strides of the operand (bf16) and of Z (floats)
   int32_t grp0, ngrp;               // channel groups of this L
   int32_t bt0;                      // first coefficient tile of this L; tile (rt, kt) is bt0 + rt * kt_n + kt
+  int32_t xonce;                    // X_L stays in LDS for both sets (Z stored beside it at zoff)
+  int32_t zoff;                     // byte offset of Z within the big LDS region when xonce
 };
 
 struct MixDev {

@@ -50,12 +50,13 @@ template <typename T>
 __device__ __forceinline__ cptr<T> as_const(const T* p) { return (cptr<T>)p; }
 
 __device__ __forceinline__ MixL load_level(const MixL* p) {
-  static_assert(sizeof(MixL) == 12 * sizeof(int32_t), "MixL is 12 int32 fields");
+  static_assert(sizeof(MixL) == 14 * sizeof(int32_t), "MixL is 14 int32 fields");
   cptr<int32_t> q = as_const(reinterpret_cast<const int32_t*>(p));
   MixL P;
   P.nrow = uni(q[0]); P.nrow16 = uni(q[1]); P.nch = uni(q[2]); P.arow = uni(q[3]);
   P.rt = uni(q[4]); P.ct = uni(q[5]); P.kt = uni(q[6]); P.kstr = uni(q[7]); P.zstr = uni(q[8]);
-  P.grp0 = uni(q[9]); P.ngrp = uni(q[10]); P.bt0 = uni(q[11]);
+  P.grp0 = uni(q[9]); P.ngrp = uni(q[10]); P.bt0 = uni(q[11]); P.xonce = uni(q[12]);
+  P.zoff = uni(q[13]);
   return P;
 }
 
@@ -457,7 +458,7 @@ __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const fl
 #undef AP_AD_LT
 #undef AP_ALL_CASES
 
-template <int L, int RTW, int CTN>
+template <int L, int RTW, int CTN, bool XO>
 __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
                                        float* om2, unsigned char* big, float* phi_lds,
                                        const int32_t* rows_lds, const int4* mem_lds, int wave,
@@ -466,24 +467,21 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
   const int ncols = kMT * w;
   __bf16* xh = reinterpret_cast<__bf16*>(big);
   __bf16* xl = xh + (size_t)P.ct * 16 * P.kstr;
-  float* Z = reinterpret_cast<float*>(big);
-  for (int p = 0; p < 2; ++p) {
-    // coupled operand X_L: zero padding (rows past nrow up to the k tiles,
-    // columns past the tile's atoms), channel rows, A rows, constant row
-    {
-      const int kpad = P.kt * 32;
-      const int padr = kpad - P.nrow;
-      for (int q = tid; q < ncols * padr; q += kMThreads) {
-        const int o = (q / padr) * P.kstr + P.nrow + q % padr;
-        xh[o] = (__bf16)0.0f;
-        xl[o] = (__bf16)0.0f;
-      }
-      const int padc = P.ct * 16 - ncols;
-      for (int q = tid; q < padc * kpad; q += kMThreads) {
-        const int o = (ncols + q / kpad) * P.kstr + q % kpad;
-        xh[o] = (__bf16)0.0f;
-        xl[o] = (__bf16)0.0f;
-      }
+  // coupled operand X_L: zero padding (rows past nrow up to the k tiles,
+  // columns past the tile's atoms), channel rows, A rows, constant row
+  auto build_x = [&]() {
+    const int kpad = P.kt * 32;
+    const int padr = kpad - P.nrow;
+    for (int q = tid; q < ncols * padr; q += kMThreads) {
+      const int o = (q / padr) * P.kstr + P.nrow + q % padr;
+      xh[o] = (__bf16)0.0f;
+      xl[o] = (__bf16)0.0f;
+    }
+    const int padc = P.ct * 16 - ncols;
+    for (int q = tid; q < padc * kpad; q += kMThreads) {
+      const int o = (ncols + q / kpad) * P.kstr + q % kpad;
+      xh[o] = (__bf16)0.0f;
+      xl[o] = (__bf16)0.0f;
     }
     xbuild<L>(m, P, A, xh, xl, mem_lds, wave, lane);
     if (P.arow) {
@@ -500,17 +498,42 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       xh[tid * P.kstr + P.nch + m.n_max] = (__bf16)1.0f;
       xl[tid * P.kstr + P.nch + m.n_max] = (__bf16)0.0f;
     }
-    __syncthreads();
-    // Z_L of coefficient set p
-    f32x4 acc[RTW][CTN];
-    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, p);
-    __syncthreads();  // X is dead from here on
-    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
-    __syncthreads();
+  };
+  auto adjoint_set = [&](const float* Z, int p) {
     float* om = p == 0 ? om1 : om2;
     adjoint<L>(m, P, A, Z, om, phi_lds + p, rows_lds, wave, lane);
     if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
+  };
+  f32x4 acc[RTW][CTN];
+  if constexpr (XO) {
+    // X_L built once; Z_L beside it.  The contraction of set 1 reads only X,
+    // so wavefronts may start it while others finish the adjoint of set 0.
+    float* Z = reinterpret_cast<float*>(big + P.zoff);
+    build_x();
     __syncthreads();
+    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 0);
+    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
+    __syncthreads();
+    adjoint_set(Z, 0);
+    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 1);
+    __syncthreads();  // every wavefront is done with Z of set 0
+    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
+    __syncthreads();
+    adjoint_set(Z, 1);
+    __syncthreads();
+  } else {
+    float* Z = reinterpret_cast<float*>(big);
+    for (int p = 0; p < 2; ++p) {
+      build_x();
+      __syncthreads();
+      // Z_L of coefficient set p
+      gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, p);
+      __syncthreads();  // X is dead from here on
+      store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
+      __syncthreads();
+      adjoint_set(Z, p);
+      __syncthreads();
+    }
   }
 }
 
@@ -602,7 +625,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 // ---- kernel 2 (one instance per coupled rank L): coupling, folded
 // contraction and adjoint for tiles of 8 atoms; adds the tile's gradient
 // and phi terms of this L to the per-atom buffers (first rank: writes).
-template <int L, int RTW, int CTN>
+template <int L, int RTW, int CTN, bool XO>
 __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     MixDev m, const int32_t* __restrict__ n_ace_p, int n_all, const float* __restrict__ A_in,
     float* __restrict__ om_buf, float* __restrict__ phi_buf) {
@@ -674,7 +697,7 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     const int64_t base = (int64_t)tile * kMT * m.nA;
     const int next = tile + (int)gridDim.x;
     if (kEarly && next < n_tiles) fetch(next);
-    rank_L<L, RTW, CTN>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
+    rank_L<L, RTW, CTN, XO>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
     __syncthreads();
     if (!kEarly && next < n_tiles) fetch(next);
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
@@ -818,17 +841,19 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     const int32_t* na = ace_list ? n_ace : nullptr;
     for (int L = 0; L <= m.L_max; ++L) {
       const void* fn = nullptr;
+      // X_L kept for both sets when it fits beside Z_L (decided with the LDS layout)
+      const bool xo = m.lv[L].xonce != 0;
+#define AP_RANK_CASE(l, ctn)                                                                  \
+  case l:                                                                                     \
+    fn = xo ? (const void*)k_ace_rank<l, kMixRtw[l], ctn, true>                               \
+            : (const void*)k_ace_rank<l, kMixRtw[l], ctn, false>;                             \
+    break;
       switch (L) {
-        case 0: fn = (const void*)k_ace_rank<0, kMixRtw[0], 1>; break;
-        case 1: fn = (const void*)k_ace_rank<1, kMixRtw[1], 2>; break;
-        case 2: fn = (const void*)k_ace_rank<2, kMixRtw[2], 3>; break;
-        case 3: fn = (const void*)k_ace_rank<3, kMixRtw[3], 4>; break;
-        case 4: fn = (const void*)k_ace_rank<4, kMixRtw[4], 5>; break;
-        case 5: fn = (const void*)k_ace_rank<5, kMixRtw[5], 6>; break;
-        case 6: fn = (const void*)k_ace_rank<6, kMixRtw[6], 7>; break;
-        case 7: fn = (const void*)k_ace_rank<7, kMixRtw[7], 8>; break;
-        default: fn = (const void*)k_ace_rank<8, kMixRtw[8], 9>; break;
+        AP_RANK_CASE(0, 1) AP_RANK_CASE(1, 2) AP_RANK_CASE(2, 3) AP_RANK_CASE(3, 4)
+        AP_RANK_CASE(4, 5) AP_RANK_CASE(5, 6) AP_RANK_CASE(6, 7) AP_RANK_CASE(7, 8)
+        default: AP_RANK_CASE(8, 9)
       }
+#undef AP_RANK_CASE
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&om_buf,
