@@ -861,7 +861,7 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&C.off_d, &C.H_d, &C.Hi_d, &C.ortho_d, &C.grid_d, &C.cell_base_d, &C.sys_of_d,
                     &C.chunk_lo_d, &C.chunk_hi_d, &C.sys_chunk_d})
     release(*b);
-  for (Buffer* b : {&ctx->cell_big, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
+  for (Buffer* b : {&ctx->cell_big, &ctx->pos4, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
                     &ctx->ace_rows_list, &ctx->rev_ace, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
@@ -986,8 +986,11 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
   {
   PhaseTimer timer(ctx, AP_PHASE_EAM, s);
-  AP_HIP(launch_eam(*ctx, sv, pos, nl->nbr, nl->count, (int32_t)N, lambda, (double*)ctx->wfp.p,
-                    (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom, force, vir, acc, s));
+  if ((st = ensure(ctx, ctx->pos4, 32 * (size_t)std::max<int64_t>(N, 1)))) return st;
+  AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
+  AP_HIP(launch_eam(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, (int32_t)N,
+                    lambda, (double*)ctx->wfp.p, (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom,
+                    force, vir, acc, s));
   }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
@@ -1019,13 +1022,15 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
   if (!acc) AP_HIP(launch_fill_f64(e_atom, 0.0, N, s));
   if (vir) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
+  if ((st = ensure(ctx, ctx->pos4, 32 * (size_t)std::max<int64_t>(N, 1)))) return st;
+  AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
   AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
   if (ctx->precision == AP_PREC_FP64) {
     PhaseTimer timer(ctx, AP_PHASE_ACE, s);
-    AP_HIP(launch_ace(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda, ace_list,
-                      n_ace, (int32_t*)ctx->ace_row.p, (int32_t*)ctx->ace_counter.p, ctx->pair_g.p,
-                      e_atom, vir, s));
+    AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
+                      (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
+                      (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir, s));
   } else {
     const MixDev& mx = ctx->mix;
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
@@ -1035,8 +1040,8 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
       return st;
     for (int phase = 0; phase < 3; ++phase) {
       PhaseTimer timer(ctx, phase == 1 ? AP_PHASE_ACE : AP_PHASE_ACE_BOND, s);
-      AP_HIP(launch_ace_mixed(*ctx, sv, pos, nl->nbr, nl->count, nl->capacity, (int32_t)N, lambda,
-                              ace_list, n_ace, (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p,
+      AP_HIP(launch_ace_mixed(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count,
+                              nl->capacity, (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p,
                               (float*)ctx->mix_A.p, (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p,
                               e_atom, vir, s, phase));
     }

@@ -155,7 +155,7 @@ struct Ctx {
   std::vector<Buffer> owned;            // model tables
   SysCache sys;
   // scratch, grown on demand
-  Buffer cell_big;
+  Buffer cell_big, pos4;
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
@@ -242,21 +242,25 @@ hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* 
                              double dt, bool drift, hipStream_t s);
 hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s);
 // EAM (k_eam.hip)
-hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_pack_pos(int32_t n, const double* pos, double4* p4, hipStream_t s);
+hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                      const int32_t* nbr,
                       const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
                       double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
                       bool accumulate, hipStream_t s);
 // ACE (k_ace.hip)
 size_t ace_lds_bytes(const AceDev& a, int precision);
 hipError_t launch_ace_reset(int32_t* counter, hipStream_t s);
-hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                      const int32_t* nbr,
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
                       hipStream_t s);
 // phase 0: bond basis -> A; 1: coupling/contraction/adjoint -> om, phi;
 // 2: embedding, bond gradients, virial
-hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                            const int32_t* nbr,
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,

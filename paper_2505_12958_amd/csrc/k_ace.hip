@@ -26,7 +26,8 @@ constexpr int kBondChunk = 64;
 
 
 __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
-    SysView sv, AceDev a, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
+    SysView sv, AceDev a, const double* __restrict__ pos, const double4* __restrict__ pos4,
+    const int32_t* __restrict__ nbr,
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
@@ -69,8 +70,9 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
       const int nb = min(kBondChunk, c - base);
       if (tid < nb) {
         const int j = nbr[(int64_t)(base + tid) * n + i];
+        const double4 pj = pos4[j];
         double dx, dy, dz;
-        displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+        displacement(ortho, H, Hi, sv.per, xi, yi, zi, pj.x, pj.y, pj.z, dx, dy, dz);
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         double g[kMaxK], dg[kMaxK];
         cheb_basis<double>(a.K, a.rc, r, g, dg);
@@ -164,8 +166,9 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     double w9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int sl = tid; sl < c; sl += kAceThreads) {
       const int j = nbr[(int64_t)sl * n + i];
+      const double4 pj = pos4[j];
       double dx, dy, dz;
-      displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+      displacement(ortho, H, Hi, sv.per, xi, yi, zi, pj.x, pj.y, pj.z, dx, dy, dz);
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double ir = 1.0 / r;
       double g[kMaxK], dg[kMaxK];
@@ -230,7 +233,8 @@ hipError_t launch_ace_reset(int32_t* counter, hipStream_t s) {
   return launch_fill_i32(counter, 0, 1, s);
 }
 
-hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                      const int32_t* nbr,
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
@@ -247,7 +251,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                             (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, nbr,
+  hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, pos4, nbr,
                      count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
                      vir_atom);
   return hipGetLastError();

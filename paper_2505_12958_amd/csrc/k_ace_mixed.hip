@@ -546,8 +546,9 @@ constexpr int kBasisWaves = 4;
 // offsets; NM = 0: the shape is read from the model at run time.
 template <int NM, int LM, int KK>
 __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
-    SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
-    const int32_t* __restrict__ count, const int32_t* __restrict__ ace_list,
+    SysView sv, MixDev m, const double* __restrict__ pos, const double4* __restrict__ pos4,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+    const int32_t* __restrict__ ace_list,
     const int32_t* __restrict__ n_ace_p, int n_all, float* __restrict__ A_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
@@ -574,7 +575,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
       const int j = nbr[(int64_t)s * n + a];
       double dx, dy, dz;
       displacement(sv.ortho[sy] != 0, sv.H + 9 * sy, sv.Hi + 9 * sy, sv.per, pos[a], pos[n + a],
-                   pos[2 * n + a], pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+                   pos[2 * n + a], pos4[j].x, pos4[j].y, pos4[j].z, dx, dy, dz);
       const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
       const float r = sqrtf(fx * fx + fy * fy + fz * fz);
       float g[kMaxK], dg[kMaxK];
@@ -714,8 +715,9 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
 // ---- kernel 3: embedding (FP64), bond gradients and virial, one wavefront per atom
 template <int NM, int LM, int KK>
 __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
-    SysView sv, MixDev m, const double* __restrict__ pos, const int32_t* __restrict__ nbr,
-    const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
+    SysView sv, MixDev m, const double* __restrict__ pos, const double4* __restrict__ pos4,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ count, int cap,
+    const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     const float* __restrict__ A_in, const float* __restrict__ om_in,
     const float* __restrict__ phi_in, float* __restrict__ pair_g, double* __restrict__ e_atom,
@@ -763,7 +765,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     const int j = nbr[(int64_t)s * n + a];
     double dx, dy, dz;
     displacement(sv.ortho[sy] != 0, sv.H + 9 * sy, sv.Hi + 9 * sy, sv.per, pos[a], pos[n + a],
-                 pos[2 * n + a], pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+                 pos[2 * n + a], pos4[j].x, pos4[j].y, pos4[j].z, dx, dy, dz);
     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
     const float r = sqrtf(fx * fx + fy * fy + fz * fz);
     const float ir = 1.f / r;
@@ -813,7 +815,8 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
 
 size_t ace_mixed_lds_bytes(const MixDev& m) { return m.big_off + m.big_bytes; }
 
-hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                            const int32_t* nbr,
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
@@ -825,8 +828,8 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     if (n_atoms == 0) return hipSuccess;
     const size_t lds = (size_t)kBasisWaves * 64 * (m.nnl + m.nlm) * 4;
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr, count,
-                         ace_list, n_ace, n_atoms, A_buf);
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
+                         count, ace_list, n_ace, n_atoms, A_buf);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_basis<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_basis<6, 3, 6>);
@@ -865,9 +868,9 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     if (n_atoms == 0) return hipSuccess;
     const size_t lds = (size_t)kBasisWaves * m.apad * 4;
     auto go = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, nbr, count,
-                         cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf, pair_g,
-                         e_atom, vir_atom);
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
+                         count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf,
+                         pair_g, e_atom, vir_atom);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_grad<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_grad<6, 3, 6>);

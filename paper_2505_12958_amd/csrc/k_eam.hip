@@ -32,7 +32,7 @@ __device__ __forceinline__ void tab_eval(const TableDev& t, double x, bool linea
 }
 
 __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t, TableDev F_t,
-                                                     const double* __restrict__ pos,
+                                                     const double4* __restrict__ pos4,
                                                      const int32_t* __restrict__ nbr,
                                                      const int32_t* __restrict__ count,
                                                      const double* __restrict__ lambda,
@@ -53,13 +53,15 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
-  const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+  const double4 pi = pos4[i];
   const int c = count[i];
   double rho = 0.0;
+#pragma unroll 2
   for (int q = 0; q < c; ++q) {
     const int j = nbr[(int64_t)q * n + i];
+    const double4 pj = pos4[j];
     double dx, dy, dz;
-    displacement(ortho, H, Hi, sv.per, xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+    displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     double v, dv;
     tab_eval(rho_t, r, false, v, dv);
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
 }
 
 __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, TableDev phi_t,
-                                                   const double* __restrict__ pos,
+                                                   const double4* __restrict__ pos4,
                                                    const int32_t* __restrict__ nbr,
                                                    const int32_t* __restrict__ count,
                                                    const double* __restrict__ wfp,
@@ -88,17 +90,19 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
-  const double xk = pos[k], yk = pos[n + k], zk = pos[2 * n + k];
+  const double4 pk = pos4[k];
   const double wk = wgt[k], fk = wfp[k];
   const int c = count[k];
   double fx = 0, fy = 0, fz = 0, ephi = 0;
   double v00 = 0, v01 = 0, v02 = 0, v10 = 0, v11 = 0, v12 = 0, v20 = 0, v21 = 0, v22 = 0;
+#pragma unroll 2
   for (int q = 0; q < c; ++q) {
     const int j = nbr[(int64_t)q * n + k];
     const double wj = wgt[j], fj = wfp[j];
     if (wk == 0.0 && wj == 0.0) continue;
+    const double4 pj = pos4[j];
     double dx, dy, dz;
-    displacement(ortho, H, Hi, sv.per, xk, yk, zk, pos[j], pos[n + j], pos[2 * n + j], dx, dy, dz);
+    displacement(ortho, H, Hi, sv.per, pk.x, pk.y, pk.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double ir = 1.0 / r;
     double z, dzr, p, dp;
@@ -135,15 +139,17 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
   }
 }
 
-hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const int32_t* nbr,
+hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
+                      const int32_t* nbr,
                       const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
                       double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
                       bool accumulate, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const dim3 g((n_atoms + 255) / 256), b(256);
-  hipLaunchKernelGGL(k_eam_density, g, b, 0, s, sv, c.rho, c.F, pos, nbr, count, lambda, wfp, eF,
+  (void)pos;
+  hipLaunchKernelGGL(k_eam_density, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda, wfp, eF,
                      wgt);
-  hipLaunchKernelGGL(k_eam_force, g, b, 0, s, sv, c.rho, c.phi, pos, nbr, count, wfp, eF, wgt,
+  hipLaunchKernelGGL(k_eam_force, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF, wgt,
                      e_atom, force, vir_atom, accumulate ? 1 : 0);
   return hipGetLastError();
 }

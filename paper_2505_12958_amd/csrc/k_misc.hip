@@ -308,4 +308,18 @@ hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hi
   return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// positions as one 32-byte record per atom: a neighbour's position is one
+// gathered load instead of three
+__global__ void k_pack_pos(int n, const double* __restrict__ pos, double4* __restrict__ p4) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p4[i] = make_double4(pos[i], pos[n + i], pos[2 * n + i], 0.0);
+}
+
+hipError_t launch_pack_pos(int32_t n, const double* pos, double4* p4, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_pos, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, p4);
+  return hipGetLastError();
+}
+
 }  // namespace ap
