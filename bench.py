@@ -13,7 +13,13 @@ timed region starts.
 
 Prints one JSON line.  value = atoms x steps / wall time of the timed steps.
 The relative force error of the timed precision against the FP64 path is
-measured on the same positions before timing; the FP64 path is timed too.
+measured on the same positions before timing; the FP64 path is timed too
+(--fp64-steps 0 skips that timing).
+
+Other workloads and the paper's AP-versus-ACE comparison:
+--workload k selects one of the five synthetic workloads (5: the static
+2.66M-atom slab); --mode ace / eam replaces the switching rule by lambda = 1
+(pure ACE) / lambda = 0 (pure EAM) on the same atoms.
 """
 from __future__ import annotations
 
@@ -35,6 +41,8 @@ def parse():
     p.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     p.add_argument("--fp64-steps", type=int, default=5)
     p.add_argument("--workload", type=int, default=3)
+    p.add_argument("--mode", choices=["ap", "ace", "eam"], default="ap",
+                   help="ap: the workload's switching rule; ace / eam: lambda = 1 / 0 everywhere")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="budget of the oracle CPU-baseline sample (0 disables)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -134,6 +142,16 @@ def cpu_baseline(wl, budget_s):
     }
 
 
+def describe(wl, mode, n_ace):
+    m = wl.ace
+    model = f"ACE n_max={m.n_max} l_max={m.l_max} nu<={m.nu_max}" if m is not None else "no ACE"
+    lam = {"ap": "the switching rule", "ace": "lambda = 1 (pure ACE)", "eam": "lambda = 0 (pure EAM)"}[mode]
+    kind = "indentation slab" if wl.n_systems == 1 and not all(wl.periodic) else (
+        "periodic bulk" if wl.n_systems == 1 else f"batch of {wl.n_systems} triclinic cells")
+    return (f"{wl.name}: {kind}, {wl.n_atoms} atoms, {model}, {lam}, {n_ace} ACE-active atoms, "
+            f"neighbours rebuilt every step, velocity-Verlet dt={wl.dt:g} fs")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -147,6 +165,8 @@ def main():
 
     t_setup = time.perf_counter()
     wl = workloads.workload(args.workload)
+    if args.mode != "ap":
+        wl.rule = workloads.LambdaRule(workloads.LAMBDA_CONST, value=1.0 if args.mode == "ace" else 0.0)
     N = wl.n_atoms
     log(f"workload {wl.name}: {N} atoms, setup {time.perf_counter() - t_setup:.1f}s")
 
@@ -179,11 +199,13 @@ def main():
 
     st, dt, prof = timed_steps(ap, torch, ctx, wl, args.steps, args.warmup, profile=True)
     value = N * args.steps / dt
-    if prec != ap.AP_PREC_FP64:
+    if prec != ap.AP_PREC_FP64 and args.fp64_steps > 0:
         _, dt64, _ = timed_steps(ap, torch, ctx64, wl, args.fp64_steps, 1, profile=False)
         v64 = N * args.fp64_steps / dt64
-    else:
+    elif prec == ap.AP_PREC_FP64:
         v64 = value
+    else:
+        v64 = None
 
     # dominant kernel: the ACE contraction phase (FP64: k_ace_fp64, which also
     # does the bond basis; mixed: the nine k_ace_rank<L> launches, bracketed
@@ -196,14 +218,14 @@ def main():
     else:
         flops = ctx.info("ace.flops_atom") * n_ace
         bound, peak, kernel = "mfma", PEAK["bf16_mfma"], "k_ace_rank<L>, L=0..8"
-    achieved = flops / avg_s / 1e12
+    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": None, "kernel": kernel,
             "kernel_avg_ms": avg_s * 1e3, "flops_per_launch": flops}
     if prec != ap.AP_PREC_FP64:
         ex = ctx.info("ace.mfma_flops_atom") * n_ace
         roof["mfma_executed_flops"] = ex
-        roof["mfma_executed_frac"] = ex / avg_s / 1e12 / peak
+        roof["mfma_executed_frac"] = ex / avg_s / 1e12 / peak if avg_s > 0 else 0.0
     phases = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
 
     line = {
@@ -213,15 +235,14 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == ap.AP_PREC_FP64 else "mixed(f32+bf16x3 mfma, f64 sums/embedding/vv)",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: BCC W-like indentation slab 50^3 cells, {N} atoms, "
-                               f"ACE n_max=8 l_max=4 nu<=4, {n_ace} ACE-active atoms, "
-                               "rebuild neighbours every step, velocity-Verlet dt=2 fs"},
+        "config": {"workload": describe(wl, args.mode, n_ace)},
         "force_rel_err_vs_fp64": err_f, "energy_rel_err_vs_fp64": err_e,
-        "virial_rel_err_vs_fp64": err_w, "fp64_path_value": v64, "vs_fp64_path": value / v64,
+        "virial_rel_err_vs_fp64": err_w, "fp64_path_value": v64,
+        "vs_fp64_path": value / v64 if v64 else None,
         "phase_ms_per_call": phases,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and args.cpu_seconds > 0:
+    if not args.no_cpu_baseline and args.cpu_seconds > 0 and args.mode == "ap" and args.workload == 3:
         log("timing the CPU oracle sample ...")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     else:
