@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     const double4* __restrict__ cell_pos, int32_t* __restrict__ nbr, int32_t* __restrict__ count,
     int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_cells) {
   __shared__ double4 cpos[kMaxCand];
-  __shared__ int list[kCellWaves][kListLds];
+  __shared__ __align__(16) int list[kCellWaves][kListLds + 4];
   __shared__ int st_cell[32];
   __shared__ int st_pre[33];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -355,12 +355,16 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
       }
       cnt += __popcll(b);
     }
-    __syncwarp_ap();
     const int m = cnt < kListLds ? cnt : kListLds;
+    if (lane < 4) lw[m + lane] = 0x7fffffff;  // sentinels: the rank loop reads whole int4
+    __syncwarp_ap();
     for (int e = lane; e < m; e += 64) {
       const int v = lw[e];
       int rank = 0;
-      for (int q = 0; q < m; ++q) rank += lw[q] < v;
+      for (int q = 0; q < m; q += 4) {
+        const int4 u = *reinterpret_cast<const int4*>(lw + q);
+        rank += (u.x < v) + (u.y < v) + (u.z < v) + (u.w < v);
+      }
       if (rank < cap) nbr[(int64_t)rank * n + i] = v;
     }
     if (lane == 0) {
