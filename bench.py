@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="budget of the oracle CPU-baseline sample (0 disables)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--pmc-probe", action="store_true",
+                   help="for rocprofv3 --pmc runs: a 256 MiB elementwise kernel (counter "
+                        "calibration), then three mixed force evaluations; prints nothing else")
     return p.parse_args()
 
 
@@ -142,6 +145,22 @@ def cpu_baseline(wl, budget_s):
     }
 
 
+def recorded_traffic(prec, ap):
+    """HBM bytes of one pass of the rank kernels from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy-type kernel), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    rec = os.path.join(here, "profiles", "ace_rank_traffic.json")
+    if prec == ap.AP_PREC_FP64 or not os.path.exists(rec):
+        return None
+    with open(rec) as f:
+        d = json.load(f)
+    with open(os.path.join(here, d["kernel_source"]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return d["traffic_bytes"] if sha == d["kernel_source_sha256"] else None
+
+
 def describe(wl, mode, n_ace):
     m = wl.ace
     model = f"ACE n_max={m.n_max} l_max={m.l_max} nu<={m.nu_max}" if m is not None else "no ACE"
@@ -162,6 +181,20 @@ def main():
     import torch
 
     from paper_2505_12958_amd import ap, workloads
+
+    if args.pmc_probe:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.mul(x, 2.0, out=y)  # reads 256 MiB, writes 256 MiB
+        wl = workloads.workload(args.workload)
+        ctx = ap.Context(wl.eam, wl.ace, ap.AP_PREC_MIXED)
+        st = ap.MD(wl)
+        for _ in range(3):
+            ctx.step(st.sys, st, 0)
+        torch.cuda.synchronize()
+        return
 
     t_setup = time.perf_counter()
     wl = workloads.workload(args.workload)
@@ -220,7 +253,7 @@ def main():
         bound, peak, kernel = "mfma", PEAK["bf16_mfma"], "k_ace_rank<L>, L=0..8"
     achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel": kernel,
+            "frac": achieved / peak, "traffic": recorded_traffic(prec, ap), "kernel": kernel,
             "kernel_avg_ms": avg_s * 1e3, "flops_per_launch": flops}
     if prec != ap.AP_PREC_FP64:
         ex = ctx.info("ace.mfma_flops_atom") * n_ace
