@@ -156,9 +156,15 @@ def recorded_traffic(prec, ap):
         return None
     with open(rec) as f:
         d = json.load(f)
-    with open(os.path.join(here, d["kernel_source"]), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    return d["traffic_bytes"] if sha == d["kernel_source_sha256"] else None
+    # the kernels' traffic depends on their source and on the host-side plan
+    # (tiles, strides, which ranks keep X_L), so every listed file is hashed
+    if "kernel_sources" not in d or "sources_sha256" not in d:
+        return None
+    h = hashlib.sha256()
+    for src in d["kernel_sources"]:
+        with open(os.path.join(here, src), "rb") as f:
+            h.update(f.read())
+    return d["traffic_bytes"] if h.hexdigest() == d["sources_sha256"] else None
 
 
 def describe(wl, mode, n_ace):

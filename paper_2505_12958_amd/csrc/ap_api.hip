@@ -565,9 +565,10 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     P.arow = a.has_arow[L];
     const int kpad = (P.nrow + 31) / 32 * 32;
     P.kt = kpad / 32;
-    // column stride of the operand in LDS: 4 dwords mod 32 banks, so the
-    // 16-byte operand reads of 8 consecutive columns hit distinct banks
-    P.kstr = kpad + (kpad % 64 == 0 ? 8 : 40);
+    // column stride of the operand in LDS: kpad/2 is a multiple of 16 dwords,
+    // so the stride is 4 or 20 dwords mod 32 banks (an odd multiple of 4) and
+    // the 16-byte operand reads of 8 consecutive columns hit distinct banks
+    P.kstr = kpad + 8;
     P.ct = (8 * w + 15) / 16;
     P.rt = 2 * P.nrow16 / 16;
     P.zstr = 8 * w + 1;

@@ -14,6 +14,8 @@
 // The folded matrix C_L collects every product-basis function: nu=4 terms
 // sit in the channel-channel block, nu=3 in the channel-A block, nu=2 and
 // nu=1 against the constant row, so one quadratic form per L gives phi.
+#include <algorithm>
+
 #include "ace_basis.h"
 #include "ap_internal.h"
 #include "geom.h"
@@ -25,6 +27,40 @@ constexpr int kAceThreads = 256;
 constexpr int kBondChunk = 64;
 
 
+// Z^(p) = C^(p) X for both coefficient sets, one folded row per thread with
+// all 2L+1 components: each stored coefficient is read once per row and used
+// for every component.  The sum over a row runs in storage order.
+template <int W>
+__device__ __forceinline__ void contract_rows(const int* __restrict__ cptr,
+                                              const int* __restrict__ ccol,
+                                              const double2* __restrict__ cval, const double* X,
+                                              double* Z1, double* Z2, int nr, int tid, double& p1,
+                                              double& p2) {
+  for (int row = tid; row < nr; row += kAceThreads) {
+    double z1[W], z2[W];
+#pragma unroll
+    for (int M = 0; M < W; ++M) { z1[M] = 0.0; z2[M] = 0.0; }
+    const int q1 = cptr[row + 1];
+    for (int q = cptr[row]; q < q1; ++q) {
+      const double2 cv = cval[q];
+      const double* xc = X + ccol[q] * W;
+#pragma unroll
+      for (int M = 0; M < W; ++M) {
+        const double x = xc[M];
+        z1[M] += cv.x * x;
+        z2[M] += cv.y * x;
+      }
+    }
+#pragma unroll
+    for (int M = 0; M < W; ++M) {
+      Z1[row * W + M] = z1[M];
+      Z2[row * W + M] = z2[M];
+      p1 += 0.5 * X[row * W + M] * z1[M];
+      p2 += 0.5 * X[row * W + M] * z2[M];
+    }
+  }
+}
+
 __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     SysView sv, AceDev a, const double* __restrict__ pos, const double4* __restrict__ pos4,
     const int32_t* __restrict__ nbr,
@@ -34,15 +70,18 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     double* __restrict__ vir) {
   extern __shared__ double lds[];
   const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
-  double* Rs = lds;                              // [64][nnl]
-  double* Ys = Rs + kBondChunk * nnl;            // [64][nlm]
-  double* A = Ys + kBondChunk * nlm;             // [nA]
+  double* A = lds;                               // [nA]
   double* om1 = A + nA;                          // [nA]
   double* om2 = om1 + nA;                        // [nA]
-  double* X = om2 + nA;                          // [xs]
+  double* red = om2 + nA;                        // [16]
+  // the bond staging of the A phase and the rank buffers share one region:
+  // the two phases never overlap, so the workgroup's LDS (and with it the
+  // number of resident workgroups per CU) is set by the larger of the two
+  double* Rs = red + 16;                         // [64][nnl]
+  double* Ys = Rs + kBondChunk * nnl;            // [64][nlm]
+  double* X = red + 16;                          // [xs]
   double* Z1 = X + xs;                           // [xs]
   double* Z2 = Z1 + xs;                          // [xs]
-  double* red = Z2 + xs;                         // [16]
   __shared__ int s_item;
   const int tid = threadIdx.x;
   const int n = sv.n_atoms;
@@ -120,19 +159,14 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
       }
       __syncthreads();
       const int* cptr = a.cx_ptr + a.cx_off[L];
-      for (int e = tid; e < nr * w; e += kAceThreads) {
-        const int row = e / w, M = e % w;
-        double z1 = 0.0, z2 = 0.0;
-        for (int q = cptr[row]; q < cptr[row + 1]; ++q) {
-          const double2 cv = a.cx_val[q];
-          const double x = X[a.cx_col[q] * w + M];
-          z1 += cv.x * x;
-          z2 += cv.y * x;
-        }
-        Z1[e] = z1;
-        Z2[e] = z2;
-        p1 += 0.5 * X[e] * z1;
-        p2 += 0.5 * X[e] * z2;
+      switch (L) {
+#define AP_CONTRACT_CASE(LL) \
+  case LL: contract_rows<2 * LL + 1>(cptr, a.cx_col, a.cx_val, X, Z1, Z2, nr, tid, p1, p2); break;
+        AP_CONTRACT_CASE(0) AP_CONTRACT_CASE(1) AP_CONTRACT_CASE(2) AP_CONTRACT_CASE(3)
+        AP_CONTRACT_CASE(4) AP_CONTRACT_CASE(5) AP_CONTRACT_CASE(6) AP_CONTRACT_CASE(7)
+        AP_CONTRACT_CASE(8)
+#undef AP_CONTRACT_CASE
+        default: break;
       }
       __syncthreads();
       const int* aptr = a.ad_ptr + a.ad_off[L];
@@ -209,8 +243,8 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
 
 size_t ace_lds_bytes(const AceDev& a, int precision) {
   (void)precision;
-  return sizeof(double) * ((size_t)kBondChunk * (a.nnl + a.nlm) + 3 * (size_t)a.nA +
-                           3 * (size_t)a.max_xsize + 16);
+  const size_t shared = std::max((size_t)kBondChunk * (a.nnl + a.nlm), 3 * (size_t)a.max_xsize);
+  return sizeof(double) * (3 * (size_t)a.nA + 16 + shared);
 }
 
 __global__ void k_ace_rows(int n, const int32_t* __restrict__ ace_list,
