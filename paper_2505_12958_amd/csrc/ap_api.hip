@@ -361,10 +361,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   auto one_row = [&]() { return nch[0] + nmax; };
 
   // X-building CSR and adjoint lists per L
-  std::vector<int32_t> xb_ptr, xb_s1, xb_s2;
-  std::vector<double> xb_c;
-  std::vector<int32_t> ad_ptr, ad_z, ad_p;
-  std::vector<double> ad_c;
+  std::vector<int32_t> xb_ptr, ad_ptr;
+  std::vector<PairTerm> xb_t, ad_t;
   std::map<std::tuple<int, int, int>, std::vector<double>> cgcache;
   for (int L = 0; L <= Lmax; ++L) {
     const int w = 2 * L + 1;
@@ -395,24 +393,16 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
             adj[s2].emplace_back(dst, s1, c);
           }
     }
-    xb_ptr.push_back((int32_t)xb_s1.size());
+    xb_ptr.push_back((int32_t)xb_t.size());
     for (auto& r : rows) {
-      for (auto& t : r) {
-        xb_s1.push_back(std::get<0>(t));
-        xb_s2.push_back(std::get<1>(t));
-        xb_c.push_back(std::get<2>(t));
-      }
-      xb_ptr.push_back((int32_t)xb_s1.size());
+      for (auto& t : r) xb_t.push_back(PairTerm{std::get<2>(t), std::get<0>(t), std::get<1>(t)});
+      xb_ptr.push_back((int32_t)xb_t.size());
     }
     a.ad_off[L] = (int32_t)ad_ptr.size();
-    ad_ptr.push_back((int32_t)ad_z.size());
+    ad_ptr.push_back((int32_t)ad_t.size());
     for (auto& r : adj) {
-      for (auto& t : r) {
-        ad_z.push_back(std::get<0>(t));
-        ad_p.push_back(std::get<1>(t));
-        ad_c.push_back(std::get<2>(t));
-      }
-      ad_ptr.push_back((int32_t)ad_z.size());
+      for (auto& t : r) ad_t.push_back(PairTerm{std::get<2>(t), std::get<1>(t), std::get<0>(t)});
+      ad_ptr.push_back((int32_t)ad_t.size());
     }
   }
   // folded coefficient matrices: phi^(p) = 1/2 sum_L sum_M X_L[:,M]^T C_L^(p) X_L[:,M]
@@ -460,10 +450,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       cx_ptr.push_back((int32_t)cx_col.size());
     }
   }
-  if ((st = upload_owned(ctx, xb_ptr, &a.xb_ptr)) || (st = upload_owned(ctx, xb_s1, &a.xb_s1)) ||
-      (st = upload_owned(ctx, xb_s2, &a.xb_s2)) || (st = upload_owned(ctx, xb_c, &a.xb_c)) ||
-      (st = upload_owned(ctx, ad_ptr, &a.ad_ptr)) || (st = upload_owned(ctx, ad_z, &a.ad_z)) ||
-      (st = upload_owned(ctx, ad_p, &a.ad_p)) || (st = upload_owned(ctx, ad_c, &a.ad_c)) ||
+  if ((st = upload_owned(ctx, xb_ptr, &a.xb_ptr)) || (st = upload_owned(ctx, xb_t, &a.xb_t)) ||
+      (st = upload_owned(ctx, ad_ptr, &a.ad_ptr)) || (st = upload_owned(ctx, ad_t, &a.ad_t)) ||
       (st = upload_owned(ctx, cx_ptr, &a.cx_ptr)) || (st = upload_owned(ctx, cx_col, &a.cx_col)) ||
       (st = upload_owned(ctx, cx_val, &a.cx_val)))
     return st;
@@ -476,7 +464,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       xrows += a.nrow[L];
     }
     ctx->flops_contract = contract;
-    ctx->flops_atom = contract + 3.0 * xb_c.size() + 5.0 * ad_c.size();
+    ctx->flops_atom = contract + 3.0 * xb_t.size() + 5.0 * ad_t.size();
     ctx->nnz = (double)cx_col.size();
     ctx->x_rows = xrows;
     ctx->flops_bond = 12.0 * K + 6.0 * a.nnl * K + 6.0 * nA + 20.0 * nlm + 40.0;

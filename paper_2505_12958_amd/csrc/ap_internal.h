@@ -51,6 +51,13 @@ struct TableDev {
 };
 
 // ACE model folded for the device
+// one term of the FP64 path's sparse sums, read as a single 16-byte load:
+// coefficient c and the two operand indices i, j
+struct alignas(16) PairTerm {
+  double c;
+  int32_t i, j;
+};
+
 struct AceDev {
   int32_t n_max, l_max, K, nlm, nA, nnl;
   int32_t L_max;            // largest coupled L
@@ -65,9 +72,7 @@ struct AceDev {
   // CSR building X: entry e of (channel row r, M) at dst = r*(2L+1)+M
   int32_t xb_off[2 * kMaxL + 2];    // offset of the L block in xb_ptr (size nch*(2L+1)+1 each)
   const int32_t* xb_ptr;
-  const int32_t* xb_s1;
-  const int32_t* xb_s2;
-  const double* xb_c;
+  const PairTerm* xb_t;             // c A[i] A[j]
   // Cext_L CSR over rows (symmetric, both coefficient sets)
   int32_t cx_off[2 * kMaxL + 2];    // offset of the L block in cx_ptr (nrow+1 each)
   const int32_t* cx_ptr;
@@ -76,9 +81,7 @@ struct AceDev {
   // adjoint CSR over A targets: terms (z index, partner A index, coef)
   int32_t ad_off[2 * kMaxL + 2];    // offset of the L block in ad_ptr (nA+1 each)
   const int32_t* ad_ptr;
-  const int32_t* ad_z;
-  const int32_t* ad_p;
-  const double* ad_c;
+  const PairTerm* ad_t;             // c A[i] Z[j]
   int32_t max_xsize;        // max_L nrow*(2L+1)
 };
 

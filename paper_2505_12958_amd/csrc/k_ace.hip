@@ -41,6 +41,8 @@ __device__ __forceinline__ void contract_rows(const int* __restrict__ cptr,
 #pragma unroll
     for (int M = 0; M < W; ++M) { z1[M] = 0.0; z2[M] = 0.0; }
     const int q1 = cptr[row + 1];
+    // unrolled so that several coefficient loads are in flight at once
+#pragma unroll 4
     for (int q = cptr[row]; q < q1; ++q) {
       const double2 cv = cval[q];
       const double* xc = X + ccol[q] * W;
@@ -149,7 +151,11 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
         double v;
         if (row < nch) {
           v = 0.0;
-          for (int q = xptr[e]; q < xptr[e + 1]; ++q) v += a.xb_c[q] * A[a.xb_s1[q]] * A[a.xb_s2[q]];
+#pragma unroll 4
+          for (int q = xptr[e]; q < xptr[e + 1]; ++q) {
+            const PairTerm u = a.xb_t[q];
+            v += u.c * A[u.i] * A[u.j];
+          }
         } else if (a.has_arow[L] && row < nch + a.n_max) {
           v = A[(row - nch) * nlm + L * L + M];
         } else {
@@ -172,10 +178,12 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
       const int* aptr = a.ad_ptr + a.ad_off[L];
       for (int t = tid; t < nA; t += kAceThreads) {
         double g1 = om1[t], g2 = om2[t];
+#pragma unroll 4
         for (int q = aptr[t]; q < aptr[t + 1]; ++q) {
-          const double f = a.ad_c[q] * A[a.ad_p[q]];
-          g1 += f * Z1[a.ad_z[q]];
-          g2 += f * Z2[a.ad_z[q]];
+          const PairTerm u = a.ad_t[q];
+          const double f = u.c * A[u.i];
+          g1 += f * Z1[u.j];
+          g2 += f * Z2[u.j];
         }
         const int q = t % nlm;
         if (a.has_arow[L] && q >= L * L && q < (L + 1) * (L + 1)) {
