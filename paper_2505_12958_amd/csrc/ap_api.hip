@@ -853,7 +853,7 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&ctx->cell_big, &ctx->pos4, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
-                    &ctx->ace_rows_list, &ctx->rev_ace, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
+                    &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi})
     release(*b);
   delete ctx;
@@ -1038,14 +1038,30 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   {
     PhaseTimer timer(ctx, AP_PHASE_ACE_GATHER, s);
     const int32_t* rev = nl->rev;
+    // the halo array holds a stamp per atom; a new allocation, or the stamp
+    // running out of range, clears it once.  A stale entry equal to the
+    // current stamp would only make the gather visit an atom whose ACE sum is
+    // zero, so correctness never depends on the clear.
+    const void* halo_before = ctx->ace_halo.p;
+    if ((st = ensure(ctx, ctx->ace_halo, 4 * (size_t)std::max<int64_t>(N, 1)))) return st;
+    if (ctx->ace_halo.p != halo_before || ctx->halo_stamp == INT32_MAX) {
+      AP_HIP(launch_fill_i32((int32_t*)ctx->ace_halo.p, 0, (int32_t)(ctx->ace_halo.bytes / 4), s));
+      ctx->halo_stamp = 0;
+    }
+    const int32_t stamp = ++ctx->halo_stamp;
+    int32_t* halo = (int32_t*)ctx->ace_halo.p;
     if (!rev) {
-      // no full reverse index: the slots of the pairs that start at a listed atom
+      // no full reverse index: the slots of the pairs that start at a listed
+      // atom (the same pass stamps the halo)
       if ((st = ensure(ctx, ctx->rev_ace, 4 * (size_t)nl->capacity * std::max<int64_t>(N, 1)))) return st;
-      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, (int32_t*)ctx->rev_ace.p, s));
+      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, (int32_t*)ctx->rev_ace.p,
+                            halo, stamp, s));
       rev = (const int32_t*)ctx->rev_ace.p;
+    } else {
+      AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, halo, stamp, s));
     }
     AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev, nl->capacity,
-                             (const int32_t*)ctx->ace_row.p, ctx->pair_g.p, force, acc, s));
+                             (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
   }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;

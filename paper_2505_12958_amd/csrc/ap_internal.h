@@ -162,7 +162,8 @@ struct Ctx {
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
-  Buffer ace_row, pair_g, ace_counter, ace_rows_list, rev_ace;
+  Buffer ace_row, pair_g, ace_counter, ace_rows_list, rev_ace, ace_halo;
+  int32_t halo_stamp = 0;           // last stamp written into ace_halo (0: cleared)
   Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
@@ -270,10 +271,15 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             double* e_atom, double* vir_atom, hipStream_t s, int phase);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev, hipStream_t s);
+                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev,
+                          int32_t* halo, int32_t stamp, hipStream_t s);
+hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
+                           int32_t stamp, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
-                             const void* pair_g, double* force, bool accumulate, hipStream_t s);
+                             const int32_t* halo, int32_t stamp, const void* pair_g, double* force,
+                             bool accumulate, hipStream_t s);
 hipError_t launch_ace_rows(int32_t n_atoms, const int32_t* ace_list, const int32_t* n_ace,
                            int32_t* ace_row, hipStream_t s);
 

@@ -304,44 +304,92 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
 // of j in the (ascending) list of k.  Entries of pairs whose first atom is
 // not listed are left untouched (the gather never reads them).  One
 // wavefront per listed atom, one lane per slot.
+// One wavefront per listed atom j (grid-stride over the list, whose length
+// is known on the device only), one lane per slot r of j: the slot of j in
+// the row of k = nbr(j, r) by binary search over that ascending row.  The
+// same pass stamps j and every k as members of the ACE halo (see k_ace_halo).
 __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                          int32_t* __restrict__ rev) {
-  const int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+                          int32_t* __restrict__ rev, int32_t* __restrict__ halo, int32_t stamp) {
   const int lane = threadIdx.x & 63;
+  const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
   const int m = ace_list ? *n_ace : n;
-  if (item >= m) return;
-  const int j = ace_list ? ace_list[item] : item;
-  const int cj = count[j];
-  for (int r = lane; r < cj; r += 64) {
-    const int k = nbr[(int64_t)r * n + j];
-    int lo = 0, hi = count[k] - 1, pos = -1;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int v = nbr[(int64_t)mid * n + k];
-      if (v == j) { pos = mid; break; }
-      if (v < j) lo = mid + 1; else hi = mid - 1;
+  for (int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); item < m;
+       item += waves) {
+    const int j = ace_list ? ace_list[item] : item;
+    const int cj = count[j];
+    if (lane == 0) halo[j] = stamp;
+    for (int r = lane; r < cj; r += 64) {
+      const int k = nbr[(int64_t)r * n + j];
+      halo[k] = stamp;
+      int lo = 0, hi = count[k] - 1, pos = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = nbr[(int64_t)mid * n + k];
+        if (v == j) { pos = mid; break; }
+        if (v < j) lo = mid + 1; else hi = mid - 1;
+      }
+      if (pos >= 0) rev[(int64_t)pos * n + k] = r;
     }
-    if (pos >= 0) rev[(int64_t)pos * n + k] = r;
   }
 }
 
+// waves of the grid-stride kernels over the ACE list: enough to fill the chip
+// several times, independent of the total number of atoms
+constexpr int64_t kListWaves = 8192;
+
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev, hipStream_t s) {
+                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev,
+                          int32_t* halo, int32_t stamp, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
-  const int64_t threads = (int64_t)n_atoms * 64;
+  const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
   hipLaunchKernelGGL(k_rev_ace, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, rev);
+                     nbr, count, ace_list, n_ace, rev, halo, stamp);
   return hipGetLastError();
 }
 
-// F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only
+// Stamps the atoms whose ACE force sum is not empty: the listed atoms and every
+// atom in their (full, hence symmetric) neighbour rows.  Every writer stores
+// the same value, so the result does not depend on the order of the writes;
+// a fresh stamp per evaluation makes clearing the array unnecessary.
+__global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
+                           int32_t* __restrict__ halo, int32_t stamp) {
+  const int lane = threadIdx.x & 63;
+  const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
+  const int m = ace_list ? *n_ace : n;
+  for (int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); item < m;
+       item += waves) {
+    const int j = ace_list ? ace_list[item] : item;
+    const int cj = count[j];
+    if (lane == 0) halo[j] = stamp;
+    for (int r = lane; r < cj; r += 64) halo[nbr[(int64_t)r * n + j]] = stamp;
+  }
+}
+
+hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
+                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
+                           int32_t stamp, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
+  hipLaunchKernelGGL(k_ace_halo, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
+                     nbr, count, ace_list, n_ace, halo, stamp);
+  return hipGetLastError();
+}
+
+// F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only.
+// Atoms outside the halo have no ACE term: zero (or unchanged when accumulating).
 template <typename G>
 __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
                              const int32_t* __restrict__ rev, int cap, const int32_t* __restrict__ row,
+                             const int32_t* __restrict__ halo, int32_t stamp,
                              const G* __restrict__ g, double* __restrict__ force, int accumulate) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  if (halo[k] != stamp) {
+    if (!accumulate) { force[k] = 0.0; force[n + k] = 0.0; force[2 * n + k] = 0.0; }
+    return;
+  }
   const int c = count[k];
   const int rk = row[k];
   double fx = 0, fy = 0, fz = 0;
@@ -369,15 +417,16 @@ __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32
 
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
-                             const void* pair_g, double* force, bool accumulate, hipStream_t s) {
+                             const int32_t* halo, int32_t stamp, const void* pair_g,
+                             double* force, bool accumulate, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const dim3 g((n_atoms + 255) / 256), b(256);
   if (c.precision == AP_PREC_FP64)
     hipLaunchKernelGGL(k_ace_gather<double>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
-                       (const double*)pair_g, force, accumulate ? 1 : 0);
+                       halo, stamp, (const double*)pair_g, force, accumulate ? 1 : 0);
   else
     hipLaunchKernelGGL(k_ace_gather<float>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
-                       (const float*)pair_g, force, accumulate ? 1 : 0);
+                       halo, stamp, (const float*)pair_g, force, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
