@@ -181,6 +181,7 @@ static ap_status prepare_systems(Ctx* ctx, const ap_systems* sys, SysView* sv) {
     C.cutoff = sys->cutoff;
     C.n_cells = (int32_t)cells;
     C.n_chunks = (int32_t)lo.size();
+    C.all_ortho = std::all_of(ortho.begin(), ortho.end(), [](uint8_t o) { return o != 0; });
     C.valid = true;
   }
   sv->n_sys = ns;
@@ -193,6 +194,7 @@ static ap_status prepare_systems(Ctx* ctx, const ap_systems* sys, SysView* sv) {
   sv->cell_base = (const int32_t*)C.cell_base_d.p;
   sv->sys_of = (const int32_t*)C.sys_of_d.p;
   for (int k = 0; k < 3; ++k) sv->per[k] = sys->periodic[k] ? 1 : 0;
+  sv->all_ortho = C.all_ortho ? 1 : 0;
   sv->rc2 = sys->cutoff * sys->cutoff;
   return AP_OK;
 }

@@ -39,6 +39,7 @@ struct SysView {
   const int32_t* cell_base;// n_sys+1: first global cell of each system
   const int32_t* sys_of;   // per atom
   int32_t per[3];
+  int32_t all_ortho;        // every system orthorhombic (kernels may specialise)
   double rc2;
 };
 
@@ -142,6 +143,7 @@ struct SysCache {
   double cutoff = 0;
   int32_t n_cells = 0;
   int32_t n_chunks = 0;
+  bool all_ortho = false;
   // device
   Buffer off_d, H_d, Hi_d, ortho_d, grid_d, cell_base_d, sys_of_d;
   Buffer chunk_lo_d, chunk_hi_d, sys_chunk_d;  // reduction chunks

@@ -26,6 +26,20 @@ __device__ __forceinline__ double wrap_unit(double d) {
   return d > 0.5 ? d - 1.0 : (d < -0.5 ? d + 1.0 : d);
 }
 
+// d = r_j - r_i in an orthorhombic box of edge lengths (Lx, Ly, Lz).
+__device__ __forceinline__ void displacement_ortho(const int32_t* per, double Lx, double Ly,
+                                                   double Lz, double xi, double yi, double zi,
+                                                   double xj, double yj, double zj, double& dx,
+                                                   double& dy, double& dz) {
+#pragma clang fp contract(off)
+  dx = xj - xi;
+  dy = yj - yi;
+  dz = zj - zi;
+  if (per[0]) dx = wrap_half(dx, Lx);
+  if (per[1]) dy = wrap_half(dy, Ly);
+  if (per[2]) dz = wrap_half(dz, Lz);
+}
+
 // d = r_j - r_i for system box H (row-major rows = lattice vectors).
 __device__ __forceinline__ void displacement(bool ortho, const double* H, const double* Hi,
                                              const int32_t* per, double xi, double yi, double zi,
@@ -33,12 +47,7 @@ __device__ __forceinline__ void displacement(bool ortho, const double* H, const 
                                              double& dy, double& dz) {
 #pragma clang fp contract(off)
   if (ortho) {
-    dx = xj - xi;
-    dy = yj - yi;
-    dz = zj - zi;
-    if (per[0]) dx = wrap_half(dx, H[0]);
-    if (per[1]) dy = wrap_half(dy, H[4]);
-    if (per[2]) dz = wrap_half(dz, H[8]);
+    displacement_ortho(per, H[0], H[4], H[8], xi, yi, zi, xj, yj, zj, dx, dy, dz);
   } else {
     double si0, si1, si2, sj0, sj1, sj2;
     frac3(Hi, xi, yi, zi, si0, si1, si2);

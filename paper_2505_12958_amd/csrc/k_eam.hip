@@ -31,6 +31,9 @@ __device__ __forceinline__ void tab_eval(const TableDev& t, double x, bool linea
   }
 }
 
+// kOrtho: every system is orthorhombic, so the box edges are hoisted out of
+// the bond loop (same arithmetic as the general displacement)
+template <bool kOrtho>
 __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t, TableDev F_t,
                                                      const double4* __restrict__ pos4,
                                                      const int32_t* __restrict__ nbr,
@@ -53,6 +56,7 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
+  const double Lx = H[0], Ly = H[4], Lz = H[8];
   const double4 pi = pos4[i];
   const int c = count[i];
   double rho = 0.0;
@@ -61,7 +65,10 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
     const int j = nbr[(int64_t)q * n + i];
     const double4 pj = pos4[j];
     double dx, dy, dz;
-    displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+    if (kOrtho)
+      displacement_ortho(sv.per, Lx, Ly, Lz, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
+    else
+      displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     double v, dv;
     tab_eval(rho_t, r, false, v, dv);
@@ -73,6 +80,7 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
   eF[i] = Fv;
 }
 
+template <bool kOrtho>
 __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, TableDev phi_t,
                                                    const double4* __restrict__ pos4,
                                                    const int32_t* __restrict__ nbr,
@@ -90,6 +98,7 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
+  const double Lx = H[0], Ly = H[4], Lz = H[8];
   const double4 pk = pos4[k];
   const double wk = wgt[k], fk = wfp[k];
   const int c = count[k];
@@ -102,7 +111,10 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
     if (wk == 0.0 && wj == 0.0) continue;
     const double4 pj = pos4[j];
     double dx, dy, dz;
-    displacement(ortho, H, Hi, sv.per, pk.x, pk.y, pk.z, pj.x, pj.y, pj.z, dx, dy, dz);
+    if (kOrtho)
+      displacement_ortho(sv.per, Lx, Ly, Lz, pk.x, pk.y, pk.z, pj.x, pj.y, pj.z, dx, dy, dz);
+    else
+      displacement(ortho, H, Hi, sv.per, pk.x, pk.y, pk.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double ir = 1.0 / r;
     double z, dzr, p, dp;
@@ -147,10 +159,17 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
   if (n_atoms == 0) return hipSuccess;
   const dim3 g((n_atoms + 255) / 256), b(256);
   (void)pos;
-  hipLaunchKernelGGL(k_eam_density, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda, wfp, eF,
-                     wgt);
-  hipLaunchKernelGGL(k_eam_force, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF, wgt,
-                     e_atom, force, vir_atom, accumulate ? 1 : 0);
+  if (sv.all_ortho) {
+    hipLaunchKernelGGL(k_eam_density<true>, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda,
+                       wfp, eF, wgt);
+    hipLaunchKernelGGL(k_eam_force<true>, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF,
+                       wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(k_eam_density<false>, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda,
+                       wfp, eF, wgt);
+    hipLaunchKernelGGL(k_eam_force<false>, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF,
+                       wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+  }
   return hipGetLastError();
 }
 

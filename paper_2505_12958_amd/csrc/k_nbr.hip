@@ -261,8 +261,8 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_cells) {
   __shared__ double4 cpos[kMaxCand];
   __shared__ __align__(16) int list[kCellWaves][kListLds + 4];
-  __shared__ int st_cell[32];
-  __shared__ int st_pre[33];
+  __shared__ int st_src[32];   // first cell-ordered atom of each stencil cell
+  __shared__ int st_pre[33];   // exclusive prefix of the stencil cells' counts
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = blockIdx.x;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
   const int ci = c - sv.cell_base[s];
   const int cc[3] = {ci / (g[1] * g[2]), (ci / g[2]) % g[1], ci % g[2]};
   if (wave == 0) {
-    int my_cell = -1, my_cnt = 0;
+    int my_cell = -1, my_cnt = 0, my_src = 0;
     if (lane < 27) {
       const int idx[3] = {lane / 9, (lane / 3) % 3, lane % 3};
       int co[3];
@@ -302,11 +302,12 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
       if (ok) {
         my_cell = sv.cell_base[s] + (co[0] * g[1] + co[1]) * g[2] + co[2];
         my_cnt = cell_count[my_cell];
+        my_src = cell_start[my_cell];
       }
     }
     const int incl = wave_incl_scan_i32(my_cnt, lane);
     if (lane < 27) {
-      st_cell[lane] = my_cell;
+      st_src[lane] = my_src;
       st_pre[lane] = incl - my_cnt;
     }
     if (lane == 26) st_pre[27] = incl;
@@ -319,12 +320,16 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     if (tid == 0) big_cells[c] = 1;
     return;
   }
-  // candidates of the stencil, cell after cell
-  for (int k = 0; k < 27; ++k) {
-    const int cnt_k = st_pre[k + 1] - st_pre[k];
-    if (cnt_k == 0) continue;
-    const int src = cell_start[st_cell[k]], dst = st_pre[k];
-    for (int q = tid; q < cnt_k; q += kCellThreads) cpos[dst + q] = cell_pos[src + q];
+  // candidates of the stencil, cell after cell, all loads of the workgroup in
+  // one pass: candidate q belongs to the last stencil cell k with
+  // st_pre[k] <= q (that cell is not empty, as st_pre[k + 1] > q)
+  for (int q = tid; q < total; q += kCellThreads) {
+    int lo = 0, hi = 26;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (st_pre[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    cpos[q] = cell_pos[st_src[lo] + (q - st_pre[lo])];
   }
   __syncthreads();
   const bool ortho = sv.ortho[s] != 0;
