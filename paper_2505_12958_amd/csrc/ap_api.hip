@@ -881,7 +881,7 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
   if ((st = ensure(ctx, ctx->cell_count, 4 * (size_t)nc)) ||
       (st = ensure(ctx, ctx->cell_start, 4 * (size_t)nc)) ||
       (st = ensure(ctx, ctx->cell_cursor, 4 * (size_t)nc)) ||
-      (st = ensure(ctx, ctx->cell_big, 4 * (size_t)nc)) ||
+      (st = ensure(ctx, ctx->cell_big, 4 * ((size_t)N + 1))) ||
       (st = ensure(ctx, ctx->cell_of, 4 * (size_t)N)) ||
       (st = ensure(ctx, ctx->cell_atoms, 4 * (size_t)N)) ||
       (st = ensure(ctx, ctx->cell_pos, 32 * (size_t)N)) ||

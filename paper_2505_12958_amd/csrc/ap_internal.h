@@ -160,7 +160,7 @@ struct Ctx {
   std::vector<Buffer> owned;            // model tables
   SysCache sys;
   // scratch, grown on demand
-  Buffer cell_big, pos4;
+  Buffer cell_big, pos4;               // cell_big: [m, atoms of the cells too big for LDS]
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
@@ -220,7 +220,7 @@ hipError_t launch_scatter(const SysView& sv, const double* pos, const int32_t* c
 hipError_t launch_fill_nbr_cells(const SysView& sv, int32_t n_cells, const double* pos,
                                  const int32_t* cell_of, const int32_t* cell_start,
                                  const int32_t* cell_count, const double4* cell_pos, int32_t* nbr,
-                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_cells,
+                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_atoms,
                                  hipStream_t s);
 hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* cell_of,
                            const int32_t* cell_start, const int32_t* cell_count,

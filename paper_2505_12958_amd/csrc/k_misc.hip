@@ -173,24 +173,21 @@ hipError_t launch_blend(int32_t n, const double* pos, const ap_lambda_rule& rule
 
 // --------------------------------------------------------------------------
 // Deterministic per-system sums of m arrays vals[k*stride + i]: one block per
-// chunk of at most kReduceChunk atoms of one system (fixed thread-strided
-// order and fixed tree), then one thread per (system, k) adds the chunk
-// partials of its system in chunk order.
+// (chunk of at most kReduceChunk atoms of one system, k) in a fixed
+// thread-strided order and fixed tree, then one thread per (system, k) adds
+// the chunk partials of its system in chunk order.
 __global__ __launch_bounds__(256) void k_reduce_chunks(const int64_t* __restrict__ lo,
                                                        const int64_t* __restrict__ hi,
                                                        const double* __restrict__ vals, int m,
                                                        int64_t stride,
                                                        double* __restrict__ partials) {
   __shared__ double ws[4];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, k = blockIdx.y;  // one workgroup per (chunk, component)
   const int64_t a = lo[c], b = hi[c];
-  for (int k = 0; k < m; ++k) {
-    double t = 0.0;
-    for (int64_t i = a + threadIdx.x; i < b; i += 256) t += vals[k * stride + i];
-    t = block_sum_f64<4>(t, ws);
-    if (threadIdx.x == 0) partials[(int64_t)c * m + k] = t;
-    __syncthreads();
-  }
+  double t = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += 256) t += vals[k * stride + i];
+  t = block_sum_f64<4>(t, ws);
+  if (threadIdx.x == 0) partials[(int64_t)c * m + k] = t;
 }
 
 __global__ void k_reduce_systems(int n_sys, const int32_t* __restrict__ sys_chunk, int m,
@@ -209,8 +206,8 @@ hipError_t launch_reduce(const SysView& sv, int32_t n_chunks, const int64_t* chu
                          int32_t m, int64_t stride, double* partials, double* out, bool accumulate,
                          hipStream_t s) {
   if (n_chunks > 0)
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(n_chunks), dim3(256), 0, s, chunk_lo, chunk_hi, vals,
-                       m, stride, partials);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(n_chunks, m), dim3(256), 0, s, chunk_lo, chunk_hi,
+                       vals, m, stride, partials);
   const int nt = sv.n_sys * m;
   hipLaunchKernelGGL(k_reduce_systems, dim3((nt + 255) / 256), dim3(256), 0, s, sv.n_sys,
                      sys_chunk, m, partials, out, accumulate ? 1 : 0);

@@ -1,6 +1,8 @@
 // Cell-list neighbour build: binning (counting sort), 27-cell stencil with
 // the canonical FP64 test, ascending-order ELL lists and the reverse-slot
 // index.  Also the generic fill and scan primitives.
+#include <algorithm>
+
 #include "ap_internal.h"
 #include "geom.h"
 #include "scan.h"
@@ -221,15 +223,17 @@ __global__ __launch_bounds__(256) void k_fill_nbr_big(SysView sv, const double* 
                                                       int32_t* __restrict__ nbr,
                                                       int32_t* __restrict__ count, int cap,
                                                       int32_t* __restrict__ overflow,
-                                                      const int32_t* __restrict__ big_cells) {
+                                                      const int32_t* __restrict__ big_atoms) {
   __shared__ int list[kWavesPerBlock][kListLds];
   __shared__ int st_cell[kWavesPerBlock][32];
   __shared__ int st_pre[kWavesPerBlock][33];
-  const int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (i >= sv.n_atoms) return;  // whole wavefront leaves together
-  if (big_cells[cell_of[i]] == 0) return;
-  atom_list_direct(sv, pos, cell_of, cell_start, cell_count, cell_pos, nbr, count, cap, overflow, i,
-                   list, st_cell, st_pre);
+  // big_atoms = [m, atom_0, ..., atom_{m-1}]: one wavefront per listed atom,
+  // grid-stride (the loop only holds wavefront-level synchronisation)
+  const int m = big_atoms[0];
+  const int waves = gridDim.x * kWavesPerBlock;
+  for (int w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < m; w += waves)
+    atom_list_direct(sv, pos, cell_of, cell_start, cell_count, cell_pos, nbr, count, cap, overflow,
+                     big_atoms[1 + w], list, st_cell, st_pre);
 }
 
 hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* cell_of,
@@ -258,7 +262,7 @@ constexpr int kMaxCand = 512;
 __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     SysView sv, const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
     const double4* __restrict__ cell_pos, int32_t* __restrict__ nbr, int32_t* __restrict__ count,
-    int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_cells) {
+    int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_atoms) {
   __shared__ double4 cpos[kMaxCand];
   __shared__ __align__(16) int list[kCellWaves][kListLds + 4];
   __shared__ int st_src[32];   // first cell-ordered atom of each stencil cell
@@ -317,7 +321,14 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
   const int n = sv.n_atoms;
   const int first = cell_start[c];
   if (total > kMaxCand) {
-    if (tid == 0) big_cells[c] = 1;
+    // too many candidates for LDS: the cell's atoms go to the fallback
+    // kernel's list (their order there does not matter, every row is
+    // computed on its own)
+    __shared__ int s_base;
+    if (tid == 0) s_base = atomicAdd(big_atoms, n_here);
+    __syncthreads();
+    for (int a = tid; a < n_here; a += kCellThreads)
+      big_atoms[1 + s_base + a] = (int)cell_pos[first + a].w;
     return;
   }
   // candidates of the stencil, cell after cell, all loads of the workgroup in
@@ -383,16 +394,16 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
 hipError_t launch_fill_nbr_cells(const SysView& sv, int32_t n_cells, const double* pos,
                                  const int32_t* cell_of, const int32_t* cell_start,
                                  const int32_t* cell_count, const double4* cell_pos, int32_t* nbr,
-                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_cells,
+                                 int32_t* count, int32_t cap, int32_t* overflow, int32_t* big_atoms,
                                  hipStream_t s) {
   if (sv.n_atoms == 0 || n_cells == 0) return hipSuccess;
-  hipError_t e = launch_fill_i32(big_cells, 0, n_cells, s);
+  hipError_t e = launch_fill_i32(big_atoms, 0, 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_nbr_cell, dim3(n_cells), dim3(kCellThreads), 0, s, sv, cell_start,
-                     cell_count, cell_pos, nbr, count, cap, overflow, big_cells);
-  const int blocks = (sv.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock;
+                     cell_count, cell_pos, nbr, count, cap, overflow, big_atoms);
+  const int blocks = std::min((sv.n_atoms + kWavesPerBlock - 1) / kWavesPerBlock, 1024);
   hipLaunchKernelGGL(k_fill_nbr_big, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, sv, pos, cell_of,
-                     cell_start, cell_count, cell_pos, nbr, count, cap, overflow, big_cells);
+                     cell_start, cell_count, cell_pos, nbr, count, cap, overflow, big_atoms);
   return hipGetLastError();
 }
 
