@@ -725,7 +725,8 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float* om = reinterpret_cast<float*>(lds) + wave * m.apad;
+  float* om = reinterpret_cast<float*>(lds) + wave * (m.apad + kMaxLM * kMaxK);
+  float* Om = om + m.apad;  // [nlm][K]
   const int n = sv.n_atoms;
   const int n_items = ace_list ? *n_ace_p : n_all;
   const int item = blockIdx.x * kBasisWaves + wave;
@@ -760,6 +761,18 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
   const int n_max = NM ? NM : m.n_max, l_max = NM ? LM : m.l_max, K = NM ? KK : m.K;
   const int lp1 = l_max + 1, nlm = lp1 * lp1;
   const float rc = (float)m.rc;
+  // omega contracted with the radial weights once per atom:
+  // Om[lm][k] = sum_n omega_nlm W_nlk, so that for every bond
+  // sum_n omega_nlm R_nl = sum_k Om[lm][k] g_k (and likewise with g_k')
+  for (int e = lane; e < nlm * K; e += 64) {
+    const int q = e / K, k = e - q * K;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= q) ++l;
+    float acc = 0.f;
+    for (int nn = 0; nn < n_max; ++nn) acc += om[nn * nlm + q] * m.Wf[(nn * lp1 + l) * K + k];
+    Om[e] = acc;
+  }
+  __syncwarp_ap();
   double w9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int s = lane; s < c; s += 64) {
     const int j = nbr[(int64_t)s * n + a];
@@ -773,25 +786,21 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     cheb_basis<float>(K, rc, r, g, dg);
     float ca[kMaxLM], cb[kMaxLM];
 #pragma unroll
-    for (int q = 0; q < kMaxLM; ++q) { ca[q] = 0.f; cb[q] = 0.f; }
-#pragma unroll
-    for (int nn = 0; nn < (NM ? NM : kMaxN); ++nn) {
-      if (nn >= n_max) break;
-#pragma unroll
-      for (int l = 0; l <= kMaxL; ++l) {
-        if (l > l_max) break;
-        float R = 0.f, dR = 0.f;
-        const float* Wr = m.Wf + (nn * lp1 + l) * K;
+    for (int q = 0; q < kMaxLM; ++q) {
+      ca[q] = 0.f;
+      cb[q] = 0.f;
+      if (q < nlm) {
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k)
-          if (k < K) { R += Wr[k] * g[k]; dR += Wr[k] * dg[k]; }
-        const float* omn = om + nn * nlm;
-#pragma unroll
-        for (int q = l * l; q < (l + 1) * (l + 1); ++q) {
-          ca[q] += omn[q] * R;
-          cb[q] += omn[q] * dR;
-        }
+          if (k < K) {
+            const float w = Om[q * K + k];
+            ca[q] += w * g[k];
+            cb[q] += w * dg[k];
+          }
       }
+      // compiler barrier: the loads of one row stay with it, so the row's
+      // weights are the only ones live at a time
+      asm volatile("" ::: "memory");
     }
     float rad, gx, gy, gz;
     ylm_contract<float>(l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, ca, cb, rad, gx, gy, gz);
@@ -866,7 +875,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     }
   } else {
     if (n_atoms == 0) return hipSuccess;
-    const size_t lds = (size_t)kBasisWaves * m.apad * 4;
+    const size_t lds = (size_t)kBasisWaves * (m.apad + kMaxLM * kMaxK) * 4;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
                          count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf,
