@@ -555,7 +555,11 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_max = NM ? NM : m.n_max, l_max = NM ? LM : m.l_max, K = NM ? KK : m.K;
   const int lp1 = l_max + 1, nlm = lp1 * lp1, nnl = n_max * lp1, nA = n_max * nlm;
-  const int stride = nnl + nlm;
+  // per bond the Chebyshev values g_k and the harmonics Y_lm go to LDS; the
+  // wavefront sums B[k][lm] = sum_j g_k(r_j) Y_lm(u_j) and contracts with the
+  // radial weights once per atom: A_nlm = sum_k W_nlk B[k][lm]
+  const int nB = K * nlm;
+  const int stride = K + nlm;
   float* RY = reinterpret_cast<float*>(lds) + wave * 64 * stride;
   const int n = sv.n_atoms;
   const int n_items = ace_list ? *n_ace_p : n_all;
@@ -581,20 +585,14 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
       float g[kMaxK], dg[kMaxK];
       cheb_basis<float>(K, rc, r, g, dg);
 #pragma unroll
-      for (int nl = 0; nl < (NM ? NM * (LM + 1) : kMaxN * (kMaxL + 1)); ++nl) {
-        if (nl >= nnl) break;
-        float v = 0.f;
-#pragma unroll
-        for (int k = 0; k < kMaxK; ++k)
-          if (k < K) v += m.Wf[nl * K + k] * g[k];
-        o[nl] = v;
-      }
+      for (int k = 0; k < kMaxK; ++k)
+        if (k < K) o[k] = g[k];
       float Y[kMaxLM];
       const float ir = 1.f / r;
       real_ylm<float>(l_max, m.ynorm, fx * ir, fy * ir, fz * ir, r, Y, nullptr);
 #pragma unroll
       for (int q = 0; q < kMaxLM; ++q)
-        if (q < nlm) o[nnl + q] = Y[q];
+        if (q < nlm) o[K + q] = Y[q];
     } else {
       for (int q = 0; q < stride; ++q) o[q] = 0.f;
     }
@@ -603,24 +601,40 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 #pragma unroll
     for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
       const int e = lane + 64 * r;
-      if (e >= nA) break;
-      const int nn = e / nlm, lm = e % nlm;
-      int l = 0;
-      while ((l + 1) * (l + 1) <= lm) ++l;
+      if (e >= nB) break;
+      const int k = e / nlm, lm = e - k * nlm;
       float v = 0.f;
-      const float* ra = RY + nn * lp1 + l;
-      const float* ya = RY + nnl + lm;
+      const float* ga = RY + k;
+      const float* ya = RY + K + lm;
 #pragma unroll 4
-      for (int s2 = 0; s2 < nb; ++s2) v += ra[s2 * stride] * ya[s2 * stride];
+      for (int s2 = 0; s2 < nb; ++s2) v += ga[s2 * stride] * ya[s2 * stride];
       acc[r] += v;
     }
     __syncwarp_ap();
   }
+  // B through LDS (the staging area is free now), then A = W B
+  float* B = RY;
 #pragma unroll
   for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
     const int e = lane + 64 * r;
-    if (e < nA) A_out[(int64_t)item * nA + e] = acc[r];
+    if (e < nB) B[e] = acc[r];
   }
+  __syncwarp_ap();
+#pragma unroll
+  for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
+    const int e = lane + 64 * r;
+    if (e >= nA) break;
+    const int nn = e / nlm, lm = e - nn * nlm;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    const float* w = m.Wf + (nn * lp1 + l) * K;
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) v += w[k] * B[k * nlm + lm];
+    A_out[(int64_t)item * nA + e] = v;
+  }
+
 }
 
 // ---- kernel 2 (one instance per coupled rank L): coupling, folded
@@ -835,7 +849,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
   if (phase == 0) {
     if (n_atoms == 0) return hipSuccess;
-    const size_t lds = (size_t)kBasisWaves * 64 * (m.nnl + m.nlm) * 4;
+    const size_t lds = (size_t)kBasisWaves * 64 * (m.K + m.nlm) * 4;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
                          count, ace_list, n_ace, n_atoms, A_buf);
