@@ -1056,11 +1056,12 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
       // no full reverse index: the slots of the pairs that start at a listed
       // atom (the same pass stamps the halo)
       if ((st = ensure(ctx, ctx->rev_ace, 4 * (size_t)nl->capacity * std::max<int64_t>(N, 1)))) return st;
-      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, (int32_t*)ctx->rev_ace.p,
-                            halo, stamp, s));
+      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace,
+                            (const int32_t*)ctx->ace_row.p, (int32_t*)ctx->rev_ace.p, halo, stamp, s));
       rev = (const int32_t*)ctx->rev_ace.p;
     } else {
-      AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, halo, stamp, s));
+      AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace,
+                             (const int32_t*)ctx->ace_row.p, halo, stamp, s));
     }
     AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev, nl->capacity,
                              (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));

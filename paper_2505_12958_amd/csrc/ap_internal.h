@@ -273,11 +273,11 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             double* e_atom, double* vir_atom, hipStream_t s, int phase);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev,
-                          int32_t* halo, int32_t stamp, hipStream_t s);
+                          const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
+                          int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s);
 hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
-                           int32_t stamp, hipStream_t s);
+                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
+                           int32_t* halo, int32_t stamp, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
                              const int32_t* halo, int32_t stamp, const void* pair_g, double* force,

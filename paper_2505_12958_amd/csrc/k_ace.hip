@@ -307,10 +307,12 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
 // One wavefront per listed atom j (grid-stride over the list, whose length
 // is known on the device only), one lane per slot r of j: the slot of j in
 // the row of k = nbr(j, r) by binary search over that ascending row.  The
-// same pass stamps j and every k as members of the ACE halo (see k_ace_halo).
+// same pass stamps the non-listed k as members of the ACE halo (see
+// k_ace_halo).
 __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                          int32_t* __restrict__ rev, int32_t* __restrict__ halo, int32_t stamp) {
+                          const int32_t* __restrict__ row, int32_t* __restrict__ rev,
+                          int32_t* __restrict__ halo, int32_t stamp) {
   const int lane = threadIdx.x & 63;
   const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
   const int m = ace_list ? *n_ace : n;
@@ -318,10 +320,9 @@ __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t*
        item += waves) {
     const int j = ace_list ? ace_list[item] : item;
     const int cj = count[j];
-    if (lane == 0) halo[j] = stamp;
     for (int r = lane; r < cj; r += 64) {
       const int k = nbr[(int64_t)r * n + j];
-      halo[k] = stamp;
+      if (row[k] < 0) halo[k] = stamp;
       int lo = 0, hi = count[k] - 1, pos = -1;
       while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
@@ -336,25 +337,28 @@ __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t*
 
 // waves of the grid-stride kernels over the ACE list: enough to fill the chip
 // several times, independent of the total number of atoms
-constexpr int64_t kListWaves = 8192;
+constexpr int64_t kListWaves = 65536;
 
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, int32_t* rev,
-                          int32_t* halo, int32_t stamp, hipStream_t s) {
+                          const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
+                          int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
   hipLaunchKernelGGL(k_rev_ace, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, rev, halo, stamp);
+                     nbr, count, ace_list, n_ace, row, rev, halo, stamp);
   return hipGetLastError();
 }
 
-// Stamps the atoms whose ACE force sum is not empty: the listed atoms and every
-// atom in their (full, hence symmetric) neighbour rows.  Every writer stores
-// the same value, so the result does not depend on the order of the writes;
-// a fresh stamp per evaluation makes clearing the array unnecessary.
+// Stamps the atoms outside the ACE list whose ACE force sum is not empty: those
+// in the (full, hence symmetric) neighbour rows of listed atoms.  Listed atoms
+// (row >= 0) are always visited by the gather and are not stamped.  Every
+// writer stores the same value, so the result does not depend on the order of
+// the writes; a fresh stamp per evaluation makes clearing the array
+// unnecessary.
 __global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
                            const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                           int32_t* __restrict__ halo, int32_t stamp) {
+                           const int32_t* __restrict__ row, int32_t* __restrict__ halo,
+                           int32_t stamp) {
   const int lane = threadIdx.x & 63;
   const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
   const int m = ace_list ? *n_ace : n;
@@ -362,23 +366,26 @@ __global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t
        item += waves) {
     const int j = ace_list ? ace_list[item] : item;
     const int cj = count[j];
-    if (lane == 0) halo[j] = stamp;
-    for (int r = lane; r < cj; r += 64) halo[nbr[(int64_t)r * n + j]] = stamp;
+    for (int r = lane; r < cj; r += 64) {
+      const int k = nbr[(int64_t)r * n + j];
+      if (row[k] < 0) halo[k] = stamp;
+    }
   }
 }
 
 hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
-                           int32_t stamp, hipStream_t s) {
+                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
+                           int32_t* halo, int32_t stamp, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
   hipLaunchKernelGGL(k_ace_halo, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, halo, stamp);
+                     nbr, count, ace_list, n_ace, row, halo, stamp);
   return hipGetLastError();
 }
 
 // F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only.
-// Atoms outside the halo have no ACE term: zero (or unchanged when accumulating).
+// Atoms neither listed nor in the halo have no ACE term: zero (or unchanged
+// when accumulating).
 template <typename G>
 __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
                              const int32_t* __restrict__ rev, int cap, const int32_t* __restrict__ row,
@@ -386,12 +393,12 @@ __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32
                              const G* __restrict__ g, double* __restrict__ force, int accumulate) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  if (halo[k] != stamp) {
+  const int rk = row[k];
+  if (rk < 0 && halo[k] != stamp) {
     if (!accumulate) { force[k] = 0.0; force[n + k] = 0.0; force[2 * n + k] = 0.0; }
     return;
   }
   const int c = count[k];
-  const int rk = row[k];
   double fx = 0, fy = 0, fz = 0;
   for (int s = 0; s < c; ++s) {
     if (rk >= 0) {
