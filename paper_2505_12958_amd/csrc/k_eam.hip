@@ -103,7 +103,9 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
   const double wk = wgt[k], fk = wfp[k];
   const int c = count[k];
   double fx = 0, fy = 0, fz = 0, ephi = 0;
-  double v00 = 0, v01 = 0, v02 = 0, v10 = 0, v11 = 0, v12 = 0, v20 = 0, v21 = 0, v22 = 0;
+  // atom k's bond gradients are parallel to the bonds, so its virial
+  // -sum_j d (x) G_kj is symmetric: six sums
+  double v00 = 0, v01 = 0, v02 = 0, v11 = 0, v12 = 0, v22 = 0;
 #pragma unroll 2
   for (int q = 0; q < c; ++q) {
     const int j = nbr[(int64_t)q * n + k];
@@ -129,8 +131,8 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
     const double g = (fk * dzr + 0.5 * wk * dp) * ir;
     const double gx = g * dx, gy = g * dy, gz = g * dz;
     v00 -= dx * gx; v01 -= dx * gy; v02 -= dx * gz;
-    v10 -= dy * gx; v11 -= dy * gy; v12 -= dy * gz;
-    v20 -= dz * gx; v21 -= dz * gy; v22 -= dz * gz;
+    v11 -= dy * gy; v12 -= dy * gz;
+    v22 -= dz * gz;
   }
   const double e = wk > 0.0 ? wk * (eF[k] + 0.5 * ephi) : 0.0;
   if (accumulate) {
@@ -146,8 +148,8 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
   }
   if (vir) {
     vir[0 * (int64_t)n + k] = v00; vir[1 * (int64_t)n + k] = v01; vir[2 * (int64_t)n + k] = v02;
-    vir[3 * (int64_t)n + k] = v10; vir[4 * (int64_t)n + k] = v11; vir[5 * (int64_t)n + k] = v12;
-    vir[6 * (int64_t)n + k] = v20; vir[7 * (int64_t)n + k] = v21; vir[8 * (int64_t)n + k] = v22;
+    vir[3 * (int64_t)n + k] = v01; vir[4 * (int64_t)n + k] = v11; vir[5 * (int64_t)n + k] = v12;
+    vir[6 * (int64_t)n + k] = v02; vir[7 * (int64_t)n + k] = v12; vir[8 * (int64_t)n + k] = v22;
   }
 }
 
