@@ -7,18 +7,19 @@
 
 namespace ap {
 
-__device__ __forceinline__ void tab_eval(const TableDev& t, double x, bool linear_beyond,
-                                         double& v, double& dv) {
+// coef: the table's (n-1) double4 coefficients, in global memory or staged in LDS
+__device__ __forceinline__ void tab_eval(const TableDev& t, const double4* coef, double x,
+                                         bool linear_beyond, double& v, double& dv) {
   int k = (int)floor((x - t.x0) * t.inv_dx);
   k = k < 0 ? 0 : (k > t.n - 2 ? t.n - 2 : k);
   const double u = x - (t.x0 + k * t.dx);
-  const double4 c = reinterpret_cast<const double4*>(t.c)[k];
+  const double4 c = coef[k];
   v = c.x + u * (c.y + u * (c.z + u * c.w));
   dv = c.y + u * (2.0 * c.z + u * 3.0 * c.w);
   const double x_end = t.x0 + (t.n - 1) * t.dx;
   if (x > x_end) {
     if (linear_beyond) {
-      const double4 e = reinterpret_cast<const double4*>(t.c)[t.n - 2];
+      const double4 e = coef[t.n - 2];
       const double h = t.dx;
       const double ve = e.x + h * (e.y + h * (e.z + h * e.w));
       const double de = e.y + h * (2.0 * e.z + h * 3.0 * e.w);
@@ -31,9 +32,19 @@ __device__ __forceinline__ void tab_eval(const TableDev& t, double x, bool linea
   }
 }
 
+// Copies a table's coefficients into LDS (whole workgroup, before any thread
+// leaves); returns where the bond loop reads them from.
+__device__ __forceinline__ const double4* stage_table(const TableDev& t, double4* lds, bool use) {
+  const double4* g = reinterpret_cast<const double4*>(t.c);
+  if (!use) return g;
+  for (int q = threadIdx.x; q < t.n - 1; q += blockDim.x) lds[q] = g[q];
+  return lds;
+}
+
 // kOrtho: every system is orthorhombic, so the box edges are hoisted out of
-// the bond loop (same arithmetic as the general displacement)
-template <bool kOrtho>
+// the bond loop (same arithmetic as the general displacement).  kLds: the
+// pair tables are staged in LDS (dynamic shared memory sized by the host).
+template <bool kOrtho, bool kLds>
 __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t, TableDev F_t,
                                                      const double4* __restrict__ pos4,
                                                      const int32_t* __restrict__ nbr,
@@ -42,6 +53,9 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
                                                      double* __restrict__ wfp,
                                                      double* __restrict__ eF,
                                                      double* __restrict__ wgt) {
+  extern __shared__ double4 tab_lds[];
+  const double4* rho_c = stage_table(rho_t, tab_lds, kLds);
+  if (kLds) __syncthreads();
   const int n = sv.n_atoms;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -71,16 +85,16 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
       displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     double v, dv;
-    tab_eval(rho_t, r, false, v, dv);
+    tab_eval(rho_t, rho_c, r, false, v, dv);
     rho += v;
   }
   double Fv, Fp;
-  tab_eval(F_t, rho, true, Fv, Fp);
+  tab_eval(F_t, reinterpret_cast<const double4*>(F_t.c), rho, true, Fv, Fp);
   wfp[i] = w * Fp;
   eF[i] = Fv;
 }
 
-template <bool kOrtho>
+template <bool kOrtho, bool kLds>
 __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, TableDev phi_t,
                                                    const double4* __restrict__ pos4,
                                                    const int32_t* __restrict__ nbr,
@@ -91,6 +105,10 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
                                                    double* __restrict__ e_atom,
                                                    double* __restrict__ force,
                                                    double* __restrict__ vir, int accumulate) {
+  extern __shared__ double4 tab_lds[];
+  const double4* rho_c = stage_table(rho_t, tab_lds, kLds);
+  const double4* phi_c = stage_table(phi_t, tab_lds + (rho_t.n - 1), kLds);
+  if (kLds) __syncthreads();
   const int n = sv.n_atoms;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -120,8 +138,8 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double ir = 1.0 / r;
     double z, dzr, p, dp;
-    tab_eval(rho_t, r, false, z, dzr);
-    tab_eval(phi_t, r, false, p, dp);
+    tab_eval(rho_t, rho_c, r, false, z, dzr);
+    tab_eval(phi_t, phi_c, r, false, p, dp);
     const double a = ((fk + fj) * dzr + 0.5 * (wk + wj) * dp) * ir;
     fx += a * dx;
     fy += a * dy;
@@ -161,16 +179,22 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
   if (n_atoms == 0) return hipSuccess;
   const dim3 g((n_atoms + 255) / 256), b(256);
   (void)pos;
+  // pair tables in LDS when both fit in a quarter of a CU's LDS (four
+  // resident workgroups); otherwise they are read through the caches
+  const size_t rho_b = 32 * (size_t)(c.rho.n - 1), phi_b = 32 * (size_t)(c.phi.n - 1);
+  const bool lds = rho_b + phi_b <= 40 * 1024;
+  auto go = [&](auto dens, auto frc) {
+    hipLaunchKernelGGL(dens, g, b, lds ? rho_b : 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda, wfp,
+                       eF, wgt);
+    hipLaunchKernelGGL(frc, g, b, lds ? rho_b + phi_b : 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp,
+                       eF, wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+  };
   if (sv.all_ortho) {
-    hipLaunchKernelGGL(k_eam_density<true>, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda,
-                       wfp, eF, wgt);
-    hipLaunchKernelGGL(k_eam_force<true>, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF,
-                       wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+    if (lds) go(k_eam_density<true, true>, k_eam_force<true, true>);
+    else go(k_eam_density<true, false>, k_eam_force<true, false>);
   } else {
-    hipLaunchKernelGGL(k_eam_density<false>, g, b, 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda,
-                       wfp, eF, wgt);
-    hipLaunchKernelGGL(k_eam_force<false>, g, b, 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp, eF,
-                       wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+    if (lds) go(k_eam_density<false, true>, k_eam_force<false, true>);
+    else go(k_eam_density<false, false>, k_eam_force<false, false>);
   }
   return hipGetLastError();
 }
