@@ -147,3 +147,24 @@ def test_nve_energy_drift_small(model):
         es.append(etot(p, v))
     # bounded fluctuation, no secular drift beyond 2e-6 eV/atom
     assert np.abs(np.array(es) - e0).max() / n < 2e-5
+
+
+def test_forces_at_equals_full_evaluation(model, cell):
+    """forces_at (the per-atom checker of the full-size tests: bond terms of
+    the sampled atoms and of their neighbours only, forces gathered through
+    each neighbour's row) equals the forces of the full evaluation on every
+    atom of a 128-atom cell with mixed lambda, indenter off."""
+    pos, box, lam = cell
+    orc = APOracle(*model)
+    S = Systems(pos, box, [0, len(pos)], (True, True, True), 5.5)
+    out = orc.evaluate(S, lam)
+    rng = np.random.default_rng(4)
+    atoms = sorted(int(i) for i in rng.choice(len(pos), 24, replace=False))
+    F, e, rows = orc.forces_at(S, lam, atoms)
+    assert np.abs(F - out["forces"][atoms]).max() <= 1e-12 * np.abs(out["forces"]).max()
+    assert np.abs(e - out["e_atom"][atoms]).max() <= 1e-12 * np.abs(out["e_atom"]).max()
+    for i in atoms:
+        assert np.array_equal(rows[i][0], out["nl"][i][0])
+    # with the k-d-tree finder of the full-size tests as well
+    F2, _, _ = orc.forces_at(S, lam, atoms[:6], S.neighbour_finder())
+    assert np.abs(F2 - out["forces"][atoms[:6]]).max() <= 1e-12 * np.abs(out["forces"]).max()

@@ -140,3 +140,40 @@ def test_eam_bond_gradient_matches_fd(wtab):
             dm = d.copy(); dm[j, k] -= h
             fd = (wtab.energy_and_grad([dp])[0][0] - wtab.energy_and_grad([dm])[0][0]) / (2 * h)
             assert abs(fd - g[0][j, k]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_table_beyond_end_branches():
+    """Past the last knot a 'linear' table continues with its end value and
+    slope (the embedding F), a 'zero' table is 0 (Phi and zeta, whose last
+    knot is the cutoff); below the first knot the first cubic continues.
+    Checked against the closed form of the tabulated cubic."""
+    f = lambda x: 0.3 - 1.2 * x + 0.7 * x ** 2 - 0.05 * x ** 3
+    df = lambda x: -1.2 + 1.4 * x - 0.15 * x ** 2
+    x0, x1 = 1.0, 5.5
+    t = w.spline_table(f, x0, x1, 50, ("slope", df(x0)), ("slope", df(x1))).arrays()
+    x = np.array([5.5 + 1e-9, 5.6, 7.0, 12.25])
+    v, dv = evaluate(t, x, "linear")
+    assert np.allclose(v, f(x1) + df(x1) * (x - x1), rtol=0, atol=1e-11)
+    assert np.allclose(dv, df(x1), rtol=0, atol=1e-11)
+    v, dv = evaluate(t, x, "zero")
+    assert np.all(v == 0.0) and np.all(dv == 0.0)
+    xb = np.array([0.2, 0.5, 0.999])
+    v, dv = evaluate(t, xb, "linear")
+    assert np.allclose(v, f(xb), atol=1e-11) and np.allclose(dv, df(xb), atol=1e-10)
+    # the EAM oracle takes the linear branch for F: an atom whose density is
+    # past the end of the F table gets F_end + F'_end (rho - rho_end)
+    orc = EamOracle(w.make_eam_tables("W", noise=0.01, seed=5))
+    Ft = orc.F
+    rho_end = Ft["x0"] + (Ft["n_knots"] - 1) * Ft["dx"]
+    c = np.asarray(Ft["coef"])[-1]
+    dx = Ft["dx"]
+    F_end = c[0] + dx * (c[1] + dx * (c[2] + dx * c[3]))
+    dF_end = c[1] + dx * (2 * c[2] + 3 * dx * c[3])
+    d = np.array([[2.0, 0.0, 0.0]] * 40)      # forty bonds at 2 A: far above 2 rho_bulk
+    rho = orc.density(d)
+    assert rho > rho_end
+    E, _, g = orc.energy_and_grad([d])
+    ph, dph = evaluate(orc.phi, np.array([2.0]), "zero")
+    z, dz = evaluate(orc.rho, np.array([2.0]), "zero")
+    assert abs(E[0] - (F_end + dF_end * (rho - rho_end) + 0.5 * 40 * ph[0])) <= 1e-12 * abs(E[0])
+    assert np.allclose(g[0][:, 0], dF_end * dz[0] + 0.5 * dph[0], rtol=1e-13, atol=0)
