@@ -11,10 +11,21 @@ adjoint forces and virial, indenter, integration.  Inputs are seeded and
 synthetic (paper_2505_12958_amd.workloads) and resident in HBM when the
 timed region starts.
 
-Prints one JSON line.  value = atoms x steps / wall time of the timed steps.
-The relative force error of the timed precision against the FP64 path is
+Prints one JSON line.  value = atoms x steps / wall time of the timed steps,
+timed with the library's phase timers off.  A second, separately timed pass
+with the phase timers on gives the per-phase times and the duration of the
+rank kernels (HIP events on the launch stream) for the roofline.  The
+relative force error of the timed precision against the FP64 path is
 measured on the same positions before timing; the FP64 path is timed too
 (--fp64-steps 0 skips that timing).
+
+Roofline (algorithmic counts of the model, per phase):
+  T_roof = sum over phases of max(bytes / 8 TB/s, VALU flops / 157.3 TFLOP/s
+           (FP64: 78.6), MFMA flops / 2.5 PFLOP/s),
+where the folded contraction is charged its three split products.  The
+`roofline` object describes the dominant kernel family (the rank kernels):
+its bound is the coupling and adjoint arithmetic on the vector ALUs; the
+contraction's MFMA share is reported beside it.
 
 Other workloads and the paper's AP-versus-ACE comparison:
 --workload k selects one of the five synthetic workloads (5: the static
@@ -25,12 +36,12 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
 
-PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}
+PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "f16_mfma": 2500.0, "hbm": 8000.0}
+SPLIT_PRODUCTS = 3
 
 
 def parse():
@@ -43,8 +54,8 @@ def parse():
     p.add_argument("--workload", type=int, default=3)
     p.add_argument("--mode", choices=["ap", "ace", "eam"], default="ap",
                    help="ap: the workload's switching rule; ace / eam: lambda = 1 / 0 everywhere")
-    p.add_argument("--cpu-seconds", type=float, default=15.0,
-                   help="budget of the oracle CPU-baseline sample (0 disables)")
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
+                   help="CPU work of the oracle baseline sample, summed over cores (0 disables)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--pmc-probe", action="store_true",
                    help="for rocprofv3 --pmc runs: a 256 MiB elementwise kernel (counter "
@@ -56,16 +67,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_eval(ap, ctx, wl, st):
-    ctx.step(st.sys, st, 0)
-
-
 def rel_err(a, b):
     import torch
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-def timed_steps(ap, torch, ctx, wl, steps, warmup, profile):
+def timed_steps(torch, ap, ctx, wl, steps, warmup, profile):
     st = ap.MD(wl)
     ctx.step(st.sys, st, 0)
     for _ in range(warmup):
@@ -88,67 +95,153 @@ def timed_steps(ap, torch, ctx, wl, steps, warmup, profile):
     return st, t1 - t0, prof
 
 
-def cpu_baseline(wl, budget_s):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same slab:
-    per-atom costs of neighbour search, EAM-only atoms and ACE atoms, scaled
-    to one full force evaluation."""
+# ---------------------------------------------------------------- CPU baseline
+def host_cores():
+    """Cores this process may use, capped at the GPU machine's CPU share per GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_chunk(args):
+    """Worker: the oracle's neighbour search and bond terms for a chunk of
+    atoms of the slab (one thread)."""
+    k, atoms, kind = args
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle.ap import APOracle
     from oracle.geometry import Systems
     from oracle.switching import lambda_of
+    from paper_2505_12958_amd import workloads
 
     with threadpool_limits(limits=1):
-        S = Systems.from_workload(wl)
-        lam = lambda_of(wl.pos, wl.rule)
-        orc = APOracle(wl.eam, wl.ace)
-        rng = np.random.default_rng(7)
-        ace_atoms = np.nonzero(lam > 0)[0]
-        eam_atoms = np.nonzero(lam == 0)[0]
-        # neighbour lists of every sampled atom: k-d-tree candidates, canonical test
-        from scipy.spatial import cKDTree
-        n_ace_s = int(max(16, min(len(ace_atoms), 0.6 * budget_s / 0.02)))
-        pick_a = rng.choice(ace_atoms, size=min(n_ace_s, len(ace_atoms)), replace=False)
-        pick_e = rng.choice(eam_atoms, size=min(3000, len(eam_atoms)), replace=False)
-        sub = np.concatenate([pick_a, pick_e])
-        p = wl.pos.copy()
-        size = np.array([wl.box[0][k][k] if wl.periodic[k] else 1e9 for k in range(3)])
-        for k in range(3):
-            if not wl.periodic[k]:
-                p[:, k] -= p[:, k].min()
+        wl = _oracle_chunk.cache.get(k)
+        if wl is None:
+            wl = workloads.workload(k)
+            S = Systems.from_workload(wl)
+            _oracle_chunk.cache[k] = wl = (wl, S, S.neighbour_finder(), lambda_of(wl.pos, wl.rule),
+                                           APOracle(wl.eam, wl.ace))
+        w, S, find, lam, orc = wl
         t = time.perf_counter()
-        tree = cKDTree(np.mod(p, size), boxsize=size)
-        cand = tree.query_ball_point(np.mod(p[sub], size), wl.cutoff * (1 + 1e-6))
-        nl = {}
-        for ii, i in enumerate(sub):
-            js = np.sort(np.asarray(cand[ii], dtype=np.int64))
-            d = S.disp(int(i), js)
-            r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
-            keep = (r2 < S.rc2) & (js != i)
-            nl[int(i)] = (js[keep], d[keep])
-        t_nbr = (time.perf_counter() - t) / len(sub)
+        nl = {int(i): find(int(i)) for i in atoms}
+        if kind != "nbr":
+            orc.bond_terms(S, lam, [int(i) for i in atoms], nl)
+        return time.perf_counter() - t
+
+
+_oracle_chunk.cache = {}
+
+
+def start_pool(cores):
+    """Worker processes for the oracle baseline, forked before anything in
+    this process touches the GPU; each loads the workload once."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    return ctx.Pool(cores)
+
+
+def cpu_baseline(pool, cores, wl, k, lam, budget_s):
+    """The FP64 oracle on all `cores` host cores (one worker process each), on
+    a bounded sample of the same slab: neighbour search of sampled atoms, bond
+    terms of sampled EAM-only and ACE atoms.  The wall time of each sample
+    class on all cores, scaled by the class's share of one full force
+    evaluation, gives the oracle's atom-steps/s."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    ace_atoms = np.nonzero(lam > 0)[0]
+    eam_atoms = np.nonzero(lam == 0)[0]
+    # warm the workers (workload generation is not timed)
+    pool.map(_oracle_chunk, [(k, [0], "nbr")] * cores, chunksize=1)
+    # per-atom cost estimates fix the sample sizes (about budget_s of CPU work)
+    t_ace1 = pool.map(_oracle_chunk, [(k, [int(ace_atoms[0])], "ace")])[0]
+    t_eam1 = max(1e-5, pool.map(_oracle_chunk, [(k, list(eam_atoms[:50]), "eam")])[0] / 50)
+    n_ace_s = int(min(len(ace_atoms), max(cores, 0.7 * budget_s / max(t_ace1, 1e-4))))
+    n_eam_s = int(min(len(eam_atoms), max(cores * 20, 0.2 * budget_s / t_eam1)))
+    pa = rng.choice(ace_atoms, n_ace_s, replace=False)
+    pe = rng.choice(eam_atoms, n_eam_s, replace=False)
+
+    def wall(atoms, kind):
+        chunks = [(k, list(c), kind) for c in np.array_split(atoms, cores) if len(c)]
         t = time.perf_counter()
-        orc.bond_terms(S, lam, [int(i) for i in pick_e], nl)
-        t_eam = (time.perf_counter() - t) / len(pick_e)
-        t = time.perf_counter()
-        orc.bond_terms(S, lam, [int(i) for i in pick_a], nl)
-        t_ace = (time.perf_counter() - t) / len(pick_a)
+        busy = sum(pool.map(_oracle_chunk, chunks, chunksize=1))
+        return time.perf_counter() - t, busy
+
+    t_a, busy_a = wall(pa, "ace")
+    t_e, busy_e = wall(pe, "eam")
     N = wl.n_atoms
-    t_eval = N * t_nbr + len(eam_atoms) * t_eam + len(ace_atoms) * t_ace
+    # one full evaluation on all cores: each class scaled from its sample
+    t_eval = t_a * len(ace_atoms) / n_ace_s + t_e * len(eam_atoms) / n_eam_s
     return {
-        "value": N / t_eval, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 numpy oracle, 1 thread: k-d-tree neighbour lists of {len(sub)} sampled atoms, "
-                   f"EAM terms of {len(pick_e)} EAM-only atoms, ACE terms of {len(pick_a)} of the "
-                   f"{len(ace_atoms)} ACE atoms of the same 250k-atom slab; per-atom costs scaled "
-                   f"to one force evaluation ({t_eval:.1f} s extrapolated)"),
+        "value": N / t_eval, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "sample": (f"FP64 numpy oracle in {cores} worker processes (one thread each, {cpu_model()}): "
+                   f"neighbour search and bond terms of {n_ace_s} of the {len(ace_atoms)} ACE atoms "
+                   f"({t_a:.1f} s wall, {busy_a:.0f} core-s) and of {n_eam_s} of the "
+                   f"{len(eam_atoms)} EAM-only atoms ({t_e:.1f} s wall) of the same slab; each "
+                   f"class scaled to its share of one full force evaluation "
+                   f"({t_eval:.1f} s extrapolated)"),
     }
 
 
-def recorded_traffic(prec, ap):
+# ---------------------------------------------------------------- roofline
+def roofline_model(ctx, ap, wl, n_ace, n_bonds, n_bonds_ace, fp64):
+    """Algorithmic T_roof per phase (seconds) of one step, from the model's
+    work counts.  Bytes are the compulsory HBM traffic of each phase: every
+    input and output array once (neighbour positions inside a bond loop are
+    gathers of arrays already counted)."""
+    N = wl.n_atoms
+    hbm = PEAK["hbm"] * 1e9
+    valu = (PEAK["fp64_valu"] if fp64 else PEAK["fp32_valu"]) * 1e12
+    f64 = PEAK["fp64_valu"] * 1e12
+    mfma = PEAK["f16_mfma"] * 1e12
+    ph = {}
+    # neighbours: positions in (24 B), cell id/perm/cell copy (4+4+32 B),
+    # list out (4 B per bond + count); canonical FP64 distance tests of ~20
+    # flops against the 27 cells around each atom, whose occupancy follows
+    # from the mean neighbour count (cells have edge r_c)
+    rc = wl.cutoff
+    occ = (n_bonds / max(1, N)) / (4.0 / 3.0 * 3.141592653589793 * rc ** 3) * rc ** 3
+    ph["neighbors"] = max((N * (24 + 40 + 4) + 4 * n_bonds) / hbm, N * 27 * occ * 20 / f64)
+    ph["blend"] = N * (24 + 8 + 4 + 1) / hbm
+    # EAM: list read in both passes, positions, per-atom rho/F'/energy/force/virial
+    ph["eam"] = max((2 * 4 * n_bonds + N * (24 + 8 * 4 + 24 + 72)) / hbm,
+                    ctx.info("eam.flops_bond") * n_bonds / f64)
+    ace_valu = ctx.info("ace.flops_atom") - ctx.info("ace.flops_contract")
+    if fp64:
+        ph["ace"] = (ctx.info("ace.flops_atom") * n_ace + ctx.info("ace.flops_bond") * n_bonds_ace) / valu
+    else:
+        ph["ace_bond"] = ctx.info("ace.flops_bond") * n_bonds_ace / valu
+        # rank kernels: coupling and adjoint on the vector ALUs, then the
+        # contraction's split products on MFMA (charged in sequence)
+        ph["ace_rank_valu"] = ace_valu * n_ace / valu
+        ph["ace_rank_mfma"] = SPLIT_PRODUCTS * ctx.info("ace.flops_contract") * n_ace / mfma
+    # gather: per ACE bond the pair gradient (12 B) and reverse slot (4 B), per atom the force
+    ph["ace_gather"] = (n_bonds_ace * 16 + N * 24) / hbm
+    ph["indenter"] = N * (24 + 1 + 24) / hbm
+    ph["integrate"] = 2 * N * (24 * 3 + 8 + 1) / hbm
+    ph["reduce"] = N * 8 * 10 / hbm
+    return ph
+
+
+def recorded_traffic(prec, ap, key):
     """HBM bytes of one pass of the rank kernels from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy-type kernel), or
-    None when the kernel source has changed since the counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy-type kernel),
+    or None when the kernel sources or the workload differ from those the
+    counters were taken on."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     rec = os.path.join(here, "profiles", "ace_rank_traffic.json")
@@ -156,9 +249,7 @@ def recorded_traffic(prec, ap):
         return None
     with open(rec) as f:
         d = json.load(f)
-    # the kernels' traffic depends on their source and on the host-side plan
-    # (tiles, strides, which ranks keep X_L), so every listed file is hashed
-    if "kernel_sources" not in d or "sources_sha256" not in d:
+    if "kernel_sources" not in d or "sources_sha256" not in d or d.get("key") != key:
         return None
     h = hashlib.sha256()
     for src in d["kernel_sources"]:
@@ -184,9 +275,17 @@ def main():
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    from paper_2505_12958_amd import workloads
+
+    want_cpu = (not args.no_cpu_baseline and args.cpu_seconds > 0 and args.mode == "ap"
+                and not args.pmc_probe)
+    cores = host_cores()
+    pool = start_pool(cores) if want_cpu else None   # before the GPU is touched
+
     import torch
 
-    from paper_2505_12958_amd import ap, workloads
+    from paper_2505_12958_amd import ap
 
     if args.pmc_probe:
         x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -195,6 +294,8 @@ def main():
         for _ in range(3):
             torch.mul(x, 2.0, out=y)  # reads 256 MiB, writes 256 MiB
         wl = workloads.workload(args.workload)
+        if args.mode != "ap":
+            wl.rule = workloads.LambdaRule(workloads.LAMBDA_CONST, value=1.0 if args.mode == "ace" else 0.0)
         ctx = ap.Context(wl.eam, wl.ace, ap.AP_PREC_MIXED)
         st = ap.MD(wl)
         for _ in range(3):
@@ -210,17 +311,9 @@ def main():
     log(f"workload {wl.name}: {N} atoms, setup {time.perf_counter() - t_setup:.1f}s")
 
     prec = ap.AP_PREC_MIXED if args.precision == "mixed" else ap.AP_PREC_FP64
+    fp64 = prec == ap.AP_PREC_FP64
     ctx64 = ap.Context(wl.eam, wl.ace, ap.AP_PREC_FP64)
-    try:
-        ctx = ap.Context(wl.eam, wl.ace, prec) if prec != ap.AP_PREC_FP64 else ctx64
-        probe = ap.MD(wl)
-        ctx.step(probe.sys, probe, 0)
-        torch.cuda.synchronize()
-    except ap.APError as e:
-        if e.status != ap.AP_ERR_UNSUPPORTED:
-            raise
-        log(f"mixed path unavailable ({e}); timing the FP64 path")
-        prec, ctx = ap.AP_PREC_FP64, ctx64
+    ctx = ctx64 if fp64 else ap.Context(wl.eam, wl.ace, prec)   # raises if unsupported
 
     # accuracy of the timed precision against the FP64 path, same positions
     ref = ap.MD(wl)
@@ -233,57 +326,75 @@ def main():
     err_w = rel_err(test.virial, ref.virial)
     n_ace = int(ref.n_ace.item())
     ace_idx = ref.ace_list[:n_ace].long()
+    n_bonds = int(ref.nl.count[:N].sum().item())
     n_bonds_ace = int(ref.nl.count[ace_idx].sum().item())
-    log(f"n_ace {n_ace}, ACE bonds {n_bonds_ace}, force err {err_f:.3e}")
+    lam = ref.lam.cpu().numpy()
+    log(f"n_ace {n_ace}, bonds {n_bonds}, ACE bonds {n_bonds_ace}, force err {err_f:.3e}")
+    del ref, test
 
-    st, dt, prof = timed_steps(ap, torch, ctx, wl, args.steps, args.warmup, profile=True)
+    # headline: phase timers off
+    _, dt, _ = timed_steps(torch, ap, ctx, wl, args.steps, args.warmup, profile=False)
     value = N * args.steps / dt
-    if prec != ap.AP_PREC_FP64 and args.fp64_steps > 0:
-        _, dt64, _ = timed_steps(ap, torch, ctx64, wl, args.fp64_steps, 1, profile=False)
+    # phases and the rank kernels' duration: a separate pass with the timers on
+    _, dt_prof, prof = timed_steps(torch, ap, ctx, wl, max(3, args.steps // 2), 1, profile=True)
+    steps_prof = max(3, args.steps // 2)
+    if not fp64 and args.fp64_steps > 0:
+        _, dt64, _ = timed_steps(torch, ap, ctx64, wl, args.fp64_steps, 1, profile=False)
         v64 = N * args.fp64_steps / dt64
-    elif prec == ap.AP_PREC_FP64:
-        v64 = value
     else:
-        v64 = None
+        v64 = value if fp64 else None
 
-    # dominant kernel: the ACE contraction phase (FP64: k_ace_fp64, which also
-    # does the bond basis; mixed: the nine k_ace_rank<L> launches, bracketed
-    # together by one pair of HIP events on the launch stream)
+    phases = {k: round(v[0] / steps_prof, 4) for k, v in prof.items() if v[1]}
     ace_ms, ace_calls = prof["ace"]
-    avg_s = ace_ms / max(1, ace_calls) * 1e-3
-    if prec == ap.AP_PREC_FP64:
+    t_rank = ace_ms / max(1, ace_calls) * 1e-3            # one pass over all coupled ranks
+    roof_ph = roofline_model(ctx, ap, wl, n_ace, n_bonds, n_bonds_ace, fp64)
+    t_roof_step = sum(roof_ph.values())
+    if fp64:
         flops = ctx.info("ace.flops_atom") * n_ace + ctx.info("ace.flops_bond") * n_bonds_ace
-        bound, peak, kernel = "alu", PEAK["fp64_valu"], "k_ace_fp64"
+        achieved = flops / t_rank / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp64_valu"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp64_valu"], "traffic": None, "kernel": "k_ace_fp64",
+                "kernel_avg_ms": t_rank * 1e3, "flops_per_launch": flops}
     else:
-        flops = ctx.info("ace.flops_atom") * n_ace
-        bound, peak, kernel = "mfma", PEAK["bf16_mfma"], "k_ace_rank<L>, L=0..8"
-    achieved = flops / avg_s / 1e12 if avg_s > 0 else 0.0
-    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": recorded_traffic(prec, ap), "kernel": kernel,
-            "kernel_avg_ms": avg_s * 1e3, "flops_per_launch": flops}
-    if prec != ap.AP_PREC_FP64:
-        ex = ctx.info("ace.mfma_flops_atom") * n_ace
-        roof["mfma_executed_flops"] = ex
-        roof["mfma_executed_frac"] = ex / avg_s / 1e12 / peak if avg_s > 0 else 0.0
-    phases = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items() if v[1]}
+        f_valu = (ctx.info("ace.flops_atom") - ctx.info("ace.flops_contract")) * n_ace
+        f_mfma = ctx.info("ace.flops_contract") * n_ace
+        a_valu = f_valu / t_rank / 1e12
+        a_mfma = f_mfma / t_rank / 1e12
+        t_roof_rank = roof_ph["ace_rank_valu"] + roof_ph["ace_rank_mfma"]
+        key = {"workload": wl.name, "mode": args.mode, "n_ace": n_ace}
+        roof = {
+            "bound": "alu", "achieved": a_valu, "peak": PEAK["fp32_valu"], "unit": "TFLOP/s",
+            "frac": a_valu / PEAK["fp32_valu"], "traffic": recorded_traffic(prec, ap, key),
+            "kernel": "k_ace_rank<L>, L=0..8 (coupling and adjoint on the vector ALUs; "
+                      "split-fp16 contraction on MFMA)",
+            "kernel_avg_ms": t_rank * 1e3, "valu_flops_per_pass": f_valu,
+            "mfma": {"achieved": a_mfma, "peak": PEAK["f16_mfma"], "unit": "TFLOP/s",
+                     "frac": a_mfma / PEAK["f16_mfma"], "flops_per_pass": f_mfma,
+                     "executed_flops_per_pass": ctx.info("ace.mfma_flops_atom") * n_ace},
+            "t_roof_ms": t_roof_rank * 1e3, "t_roof_frac": t_roof_rank / t_rank,
+        }
+    roof["step"] = {"t_roof_ms": t_roof_step * 1e3, "ms_per_step": dt / args.steps * 1e3,
+                    "frac": t_roof_step / (dt / args.steps),
+                    "phases_t_roof_ms": {k: round(v * 1e3, 5) for k, v in roof_ph.items()}}
 
     line = {
         "metric": "AP force atom-steps/s at <=1e-5 rel force err vs FP64; % roofline; vs FP64 path",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == ap.AP_PREC_FP64 else "mixed(f32+bf16x3 mfma, f64 sums/embedding/vv)",
+        "dtype": "f64" if fp64 else "mixed(f32 basis/coupling/adjoint, f16x3 split mfma, f64 sums/embedding/vv)",
         "data": "synthetic",
         "config": {"workload": describe(wl, args.mode, n_ace)},
         "force_rel_err_vs_fp64": err_f, "energy_rel_err_vs_fp64": err_e,
         "virial_rel_err_vs_fp64": err_w, "fp64_path_value": v64,
         "vs_fp64_path": value / v64 if v64 else None,
-        "phase_ms_per_call": phases,
+        "phase_ms_per_step": phases, "ms_per_step_profiled": dt_prof / steps_prof * 1e3,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and args.cpu_seconds > 0 and args.mode == "ap" and args.workload == 3:
-        log("timing the CPU oracle sample ...")
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if pool is not None:
+        log(f"timing the CPU oracle sample on {cores} cores ...")
+        line["cpu_baseline"] = cpu_baseline(pool, cores, wl, args.workload, lam, args.cpu_seconds)
+        pool.close()
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -107,8 +107,8 @@ def lib():
         L.ap_profile.argtypes = [vp, i32]
         L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
         L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
-        for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_eam_forces",
-                  "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
+        for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend",
+                  "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

@@ -477,7 +477,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     return AP_OK;
   }
 
-  // ---- mixed path: block-sparse split-bf16 tiles, channel groups
+  // ---- mixed path: dense split-fp16 tiles with power-of-two row scales, channel groups
   MixDev& x = ctx->mix;
   x.n_max = nmax; x.l_max = lmax; x.K = K; x.nlm = nlm; x.nA = nA; x.nnl = a.nnl;
   x.apad = nA | 1;
@@ -500,18 +500,19 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   std::map<std::tuple<int, int, int>, int> pat_id;
   size_t big = (size_t)4 * 64 * (a.nnl + nlm) * 4;
   std::vector<size_t> xbytes(Lmax + 1, 0), zbytes(Lmax + 1, 0);
-  auto bf16_rne = [](float f) -> uint16_t {
-    uint32_t u;
-    memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+  // fp16 round-to-nearest-even of a float and back
+  auto f16_bits = [](float f) -> uint16_t {
+    const _Float16 h = (_Float16)f;
+    uint16_t u;
+    memcpy(&u, &h, 2);
+    return u;
   };
-  auto bf16_to_f = [](uint16_t b) -> float {
-    uint32_t u = (uint32_t)b << 16;
-    float f;
-    memcpy(&f, &u, 4);
-    return f;
+  auto f16_val = [](uint16_t b) -> float {
+    _Float16 h;
+    memcpy(&h, &b, 2);
+    return (float)h;
   };
+  std::vector<float> rscale;
   // coupling coefficients of every valid (la, lb, L), over the selection-rule
   // superset in (m1, m2, M) order, addressed by key la*45 + lb*9 + L
   for (int la = 0; la <= lmax; ++la)
@@ -575,6 +576,22 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       D[((size_t)kv.first.first * P.nrow + kv.first.second) * 2 + 1] = kv.second.second;
     }
     P.bt0 = (int32_t)(ctile.size() / 128);
+    // each row of each set is scaled by 2^e so that its largest entry lies
+    // in [2^12, 2^13): the fp16 hi/lo pieces then keep 22 significant bits of
+    // every entry that matters and no product overflows; the kernel
+    // multiplies the row's results by 2^-e (exact)
+    P.rs0 = (int32_t)rscale.size();
+    std::vector<int> rexp(2 * P.nrow16, 0);
+    for (int p = 0; p < 2; ++p)
+      for (int rr = 0; rr < P.nrow16; ++rr) {
+        double mx = 0.0;
+        if (rr < P.nrow)
+          for (int k = 0; k < P.nrow; ++k) mx = std::max(mx, std::fabs(D[((size_t)rr * P.nrow + k) * 2 + p]));
+        int ex = 0;
+        if (mx > 0.0) (void)std::frexp((double)(float)mx, &ex);
+        rexp[p * P.nrow16 + rr] = mx > 0.0 ? 13 - ex : 0;
+        rscale.push_back(std::ldexp(1.0f, -rexp[p * P.nrow16 + rr]));
+      }
     for (int rt = 0; rt < P.rt; ++rt) {
       for (int kt = 0; kt < P.kt; ++kt) {
         double v[16][32];
@@ -585,7 +602,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
             const int p = r / P.nrow16, rr = r % P.nrow16;
             double val = 0.0;
             if (rr < P.nrow && k < P.nrow) val = D[((size_t)rr * P.nrow + k) * 2 + p];
-            v[i][kk] = val;
+            v[i][kk] = std::ldexp(val, rexp[r]);
             any = any || val != 0.0;
           }
         (void)any;  // all tiles are stored (the folded matrices are almost dense)
@@ -596,8 +613,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
           uint16_t hi[8], lo[8];
           for (int j = 0; j < 8; ++j) {
             const double val = v[lane % 16][8 * (lane / 16) + j];
-            hi[j] = bf16_rne((float)val);
-            lo[j] = bf16_rne((float)(val - (double)bf16_to_f(hi[j])));
+            hi[j] = f16_bits((float)val);
+            lo[j] = f16_bits((float)(val - (double)f16_val(hi[j])));
           }
           uint4 h4, l4;
           memcpy(&h4, hi, 16);
@@ -733,7 +750,8 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     }
     adj_ptr.push_back((int32_t)adj_units.size());
   }
-  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16) * 4 + 15) / 16 * 16);
+  // LDS head: A, omega of both sets, phi [8][2], per-atom norm bound [8]
+  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8) * 4 + 15) / 16 * 16);
   size_t tab = (size_t)nidx * nidx * 4;
   for (int L = 0; L <= Lmax; ++L) tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16);
   x.big_off = (int32_t)((x.tab_off + tab + 15) / 16 * 16);
@@ -747,7 +765,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   x.big_bytes = (int32_t)big;
   if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
     return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");
-  if ((st = upload_owned(ctx, ctile, &x.ctile)) ||
+  if ((st = upload_owned(ctx, ctile, &x.ctile)) || (st = upload_owned(ctx, rscale, &x.rscale)) ||
       (st = upload_owned(ctx, grp_pat, &x.grp_pat)) || (st = upload_owned(ctx, grp_mem, &x.grp_mem)) ||
       (st = upload_owned(ctx, pat_hdr, &x.pat_hdr)) || (st = upload_owned(ctx, pat_ent, &x.pat_ent)) ||
       (st = upload_owned(ctx, pat_coef, &x.pat_coef)) || (st = upload_owned(ctx, pat_off, &x.pat_off)) ||
@@ -856,7 +874,7 @@ ap_status ap_destroy(ap_ctx* c) {
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
                     &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
-                    &ctx->mix_om, &ctx->mix_phi})
+                    &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn})
     release(*b);
   delete ctx;
   return AP_OK;
@@ -916,11 +934,8 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
   return AP_OK;
 }
 
-ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_lambda_rule* rule,
-                   double* lambda, int32_t* ace_list, int32_t* n_ace, void* stream) {
-  Ctx* ctx = (Ctx*)c;
-  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
-  hipStream_t s = (hipStream_t)stream;
+static ap_status check_blend_args(Ctx* ctx, const ap_lambda_rule* rule, const double* lambda,
+                                  const int32_t* ace_list, const int32_t* n_ace) {
   if (!rule || !lambda || !ace_list || !n_ace) return fail(ctx, AP_ERR_ARG, "blend arguments missing");
   if (rule->kind < AP_LAMBDA_CONST || rule->kind > AP_LAMBDA_GIVEN) return fail(ctx, AP_ERR_ARG, "bad rule kind");
   if (rule->kind == AP_LAMBDA_CONST && !(rule->value >= 0.0 && rule->value <= 1.0))
@@ -929,7 +944,16 @@ ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap
       (!(rule->r_full >= 0) || !(rule->taper > 0)))
     return fail(ctx, AP_ERR_ARG, "rule needs r_full >= 0 and taper > 0");
   if (rule->kind == AP_LAMBDA_MASK && !rule->mask) return fail(ctx, AP_ERR_ARG, "mask rule needs a mask");
+  return AP_OK;
+}
+
+ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap_lambda_rule* rule,
+                   double* lambda, int32_t* ace_list, int32_t* n_ace, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
   ap_status st;
+  if ((st = check_blend_args(ctx, rule, lambda, ace_list, n_ace))) return st;
   SysView sv;
   if ((st = prepare_systems(ctx, sys, &sv))) return st;
   if (!pos && sv.n_atoms > 0) return fail(ctx, AP_ERR_ARG, "pos is NULL");
@@ -1027,14 +1051,14 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
     if ((st = ensure(ctx, ctx->mix_A, 4 * rows * mx.nA)) ||
         (st = ensure(ctx, ctx->mix_om, 8 * rows * mx.nA)) ||
-        (st = ensure(ctx, ctx->mix_phi, 8 * rows)))
+        (st = ensure(ctx, ctx->mix_phi, 8 * rows)) || (st = ensure(ctx, ctx->mix_bn, 4 * rows)))
       return st;
     for (int phase = 0; phase < 3; ++phase) {
       PhaseTimer timer(ctx, phase == 1 ? AP_PHASE_ACE : AP_PHASE_ACE_BOND, s);
       AP_HIP(launch_ace_mixed(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count,
                               nl->capacity, (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p,
                               (float*)ctx->mix_A.p, (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p,
-                              e_atom, vir, s, phase));
+                              (float*)ctx->mix_bn.p, e_atom, vir, s, phase));
     }
   }
   {

@@ -86,7 +86,7 @@ struct AceDev {
   int32_t max_xsize;        // max_L nrow*(2L+1)
 };
 
-// ---- mixed-precision ACE model: per-L tiling, dense split-bf16 tiles,
+// ---- mixed-precision ACE model: per-L tiling, dense split-fp16 tiles,
 // channel groups of equal (l_a, l_b) with their coupling entries
 struct CgEnt {
   int8_t m1, m2, M, pad;
@@ -102,11 +102,12 @@ constexpr int kMixRtw[2 * kMaxL + 1] = {2, 3, 3, 3, 3, 2, 2, 1, 1};
 struct MixL {
   int32_t nrow, nrow16, nch, arow;  // rows of X_L, padded to 16, channel rows, has A rows
   int32_t rt, ct, kt;               // row tiles (both sets), column tiles, k tiles
-  int32_t kstr, zstr;               // LDS strides of the operand (bf16) and of Z (floats)
+  int32_t kstr, zstr;               // LDS strides of the operand (fp16) and of Z (floats)
   int32_t grp0, ngrp;               // channel groups of this L
   int32_t bt0;                      // first coefficient tile of this L; tile (rt, kt) is bt0 + rt * kt_n + kt
   int32_t xonce;                    // X_L stays in LDS for both sets (Z stored beside it at zoff)
   int32_t zoff;                     // byte offset of Z within the big LDS region when xonce
+  int32_t rs0;                      // first row scale of this L in MixDev::rscale (set p at rs0 + p * nrow16)
 };
 
 struct MixDev {
@@ -116,7 +117,8 @@ struct MixDev {
   const double* ynorm;
   MixL lv[2 * kMaxL + 1];   // host copy
   const MixL* lv_d;         // device copy (indexed by L in the kernel)
-  const uint4* ctile;      // dense tiles: (2 * tile + split) * 64 + lane, 8 bf16 per lane
+  const uint4* ctile;      // dense tiles: (2 * tile + split) * 64 + lane, 8 fp16 per lane
+  const float* rscale;     // per coefficient row: 2^-e, the inverse of the row's power-of-two scale
   const int32_t* grp_pat;  // pattern of each group
   const int4* grp_mem;     // 8 members per group: {row, A offset of a, A offset of b, la*5+lb}
   const int32_t* pat_hdr;  // 5 ints per pattern: la, lb, L, switch key, first coefficient
@@ -167,6 +169,7 @@ struct Ctx {
   Buffer ace_row, pair_g, ace_counter, ace_rows_list, rev_ace, ace_halo;
   int32_t halo_stamp = 0;           // last stamp written into ace_halo (0: cleared)
   Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
+  Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
   size_t ace_lds = 0;
@@ -270,8 +273,13 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
-                            double* e_atom, double* vir_atom, hipStream_t s, int phase);
+                            float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
+                            int phase);
 size_t ace_mixed_lds_bytes(const MixDev& m);
+// the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
+// per L); xo: the variant that keeps X_L in LDS for both coefficient sets
+template <int L>
+const void* rank_kernel(bool xo);
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
                           int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s);

@@ -12,6 +12,10 @@ OUT = os.path.join(PKG, "libap.so")
 OBJ = os.path.join(PKG, "_build")
 
 SOURCES = ["ap_api.hip", "k_nbr.hip", "k_misc.hip", "k_eam.hip", "k_ace.hip", "k_ace_mixed.hip"]
+# (source, object name, extra flags): the mixed rank kernels are compiled once
+# per coupled rank L, in parallel
+UNITS = [(s, s.replace(".hip", ""), []) for s in SOURCES] + [
+    ("k_ace_rank.hip", f"k_ace_rank_L{L}", [f"-DAP_RANK_L={L}"]) for L in range(9)]
 ARCH = os.environ.get("AP_OFFLOAD_ARCH", "gfx950")
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -33,10 +37,11 @@ def hipcc():
     return "hipcc"
 
 
-def compile_one(src):
+def compile_one(unit):
+    src, name, flags = unit
     os.makedirs(OBJ, exist_ok=True)
-    obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-    cmd = [hipcc(), "-c", os.path.join(HERE, src), "-o", obj] + COMMON + EXTRA.get(src, [])
+    obj = os.path.join(OBJ, name + ".o")
+    cmd = [hipcc(), "-c", os.path.join(HERE, src), "-o", obj] + COMMON + EXTRA.get(src, []) + flags
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -44,9 +49,11 @@ def compile_one(src):
 
 
 def build(verbose=True):
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(compile_one, srcs))
+    units = [u for u in UNITS if os.path.exists(os.path.join(HERE, u[0]))]
+    # the largest units first, so the slowest compiles start at once
+    units.sort(key=lambda u: -os.path.getsize(os.path.join(HERE, u[0])))
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16, len(units))) as ex:
+        objs = list(ex.map(compile_one, units))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-fPIC"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,541 +1,12 @@
-// ACE part of the AP force, mixed-precision path.
-//
-// One workgroup (512 threads, 8 wavefronts, two per SIMD) evaluates tiles of 8 ACE-active
-// atoms (persistent loop, tiles assigned round-robin: every tile costs the same), on chip:
-//
-//  1. bond basis in FP32 from the FP64 minimum-image displacement; the
-//     atomic basis A_nlm of the 8 atoms is accumulated in LDS;
-//  2. per coupled rank L:
-//     a. coupling X_L = [AA_{c,M} | A_{n,L,M} | 1] for the 8 atoms (VALU;
-//        one lane per (channel, atom), channels grouped by (l_a, l_b) so the
-//        Clebsch-Gordan entries are wavefront-uniform), written to LDS as a
-//        bf16 hi/lo split (x = hi + lo to ~16 bits);
-//     b. folded contraction Z_L = C_L X_L for both coefficient sets with
-//        v_mfma_f32_16x16x32_bf16: the 16x32 tiles of C_L are stored dense
-//        (pre-split into bf16 hi/lo), each product taken as
-//        hi*hi + hi*lo + lo*hi with FP32 accumulation;
-//     c. Z_L of each set goes to LDS (over the dead X_L) and the adjoint
-//        dphi/dA = (dX_L/dA)^T Z_L is formed per (channel, atom) and added
-//        to the atom's gradient; phi itself follows from Euler's theorem
-//        for homogeneous functions (see the end of the tile loop);
-//  3. embedding E = phi1 + sqrt(|phi2| + 1e-6) and its derivative in FP64;
-//  4. per-bond gradients g_ij (FP32) and the atom's virial (FP64 sums).
+// ACE part of the AP force, mixed-precision path: bond basis (kernel 1),
+// embedding and bond gradients (kernel 3) and the launcher of the three
+// phases; the rank kernels (phase 1) are in ace_rank.h / k_ace_rank.hip.
 #include "ace_basis.h"
 #include "ap_internal.h"
 #include "geom.h"
 #include "scan.h"
 
-#include <utility>
-
 namespace ap {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kMT = 8;
-constexpr int kMWaves = kMixWaves;
-constexpr int kMThreads = 64 * kMWaves;
-
-__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-
-// Values the compiler cannot prove uniform (loads next to stores) are made
-// wavefront-uniform explicitly so they live in scalar registers.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Read-only model tables are read through the constant address space, so
-// wavefront-uniform indices become scalar loads (the kernel never writes them).
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T*;
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const T* p) { return (cptr<T>)p; }
-
-__device__ __forceinline__ MixL load_level(const MixL* p) {
-  static_assert(sizeof(MixL) == 14 * sizeof(int32_t), "MixL is 14 int32 fields");
-  cptr<int32_t> q = as_const(reinterpret_cast<const int32_t*>(p));
-  MixL P;
-  P.nrow = uni(q[0]); P.nrow16 = uni(q[1]); P.nch = uni(q[2]); P.arow = uni(q[3]);
-  P.rt = uni(q[4]); P.ct = uni(q[5]); P.kt = uni(q[6]); P.kstr = uni(q[7]); P.zstr = uni(q[8]);
-  P.grp0 = uni(q[9]); P.ngrp = uni(q[10]); P.bt0 = uni(q[11]); P.xonce = uni(q[12]);
-  P.zoff = uni(q[13]);
-  return P;
-}
-
-__device__ __forceinline__ CgEnt load_ent(const CgEnt* p) {
-  const int2 raw = *reinterpret_cast<const int2*>(p);
-  const int w0 = uni(raw.x);
-  CgEnt e;
-  e.m1 = (int8_t)(w0 & 0xff);
-  e.m2 = (int8_t)((w0 >> 8) & 0xff);
-  e.M = (int8_t)((w0 >> 16) & 0xff);
-  e.pad = 0;
-  e.c = __int_as_float(uni(raw.y));
-  return e;
-}
-
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
-// GEMM of one L for N owned row tiles (rt = wave + kMWaves i, i < N): N and
-// CTN are compile-time, so the k loop has no branches and the coefficient
-// loads of the next k tile stay in flight under this tile's MFMAs.  X is read
-// from LDS (column-major, k contiguous); the coefficient tiles stream from L2.
-template <int N, int RTW, int CTN>
-__device__ __forceinline__ void gemm_owned(const MixL& P, const uint4* base, const __bf16* xh,
-                                           const __bf16* xl, f32x4 (&acc)[RTW][CTN], int lane) {
-  static_assert(N >= 1 && N <= RTW, "owned row tiles");
-  const uint4* tp[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) tp[i] = base + (size_t)2 * 64 * kMWaves * i * P.kt;
-  const int col_l = lane & 15;
-  const int k_l = 8 * (lane >> 4);
-  // two register buffers of coefficient tiles (hi, lo), ping-pong: the tiles
-  // of k tile kt + 1 load while those of kt feed the MFMAs
-  uint4 ah[N], al[N], bh[N], bl[N];
-  auto load = [&](uint4 (&h)[N], uint4 (&l)[N], int kt) {
-    const int k = min(kt, P.kt - 1);  // past the end: reload the last tile (harmless)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      h[i] = tp[i][128 * k];
-      l[i] = tp[i][128 * k + 64];
-    }
-    // compiler barrier: keep the loads here, ahead of their use
-    asm volatile("" ::: "memory");
-  };
-  auto compute = [&](const uint4 (&h)[N], const uint4 (&l)[N], int kt) {
-#pragma unroll
-    for (int c = 0; c < CTN; ++c) {
-      const int off = (c * 16 + col_l) * P.kstr + kt * 32 + k_l;
-      const bf16x8 xbh = as_bf16x8(*reinterpret_cast<const uint4*>(xh + off));
-      const bf16x8 xbl = as_bf16x8(*reinterpret_cast<const uint4*>(xl + off));
-      // the three split products, interleaved over independent accumulators
-#pragma unroll
-      for (int sp = 0; sp < 3; ++sp) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          const bf16x8 a = as_bf16x8(sp == 2 ? l[i] : h[i]);
-          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, sp == 1 ? xbl : xbh, acc[i][c], 0, 0, 0);
-        }
-      }
-    }
-  };
-  load(ah, al, 0);
-  for (int kt = 0; kt < P.kt; kt += 2) {
-    load(bh, bl, kt + 1);
-    compute(ah, al, kt);
-    if (kt + 1 < P.kt) {
-      load(ah, al, kt + 2);
-      compute(bh, bl, kt + 1);
-    }
-  }
-}
-
-// GEMM of one L: accumulators of the wavefront's row tiles for all column tiles.
-template <int RTW, int CTN>
-__device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const __bf16* xh,
-                                           const __bf16* xl, f32x4 (&acc)[RTW][CTN], int wave,
-                                           int lane, int p) {
-  const int rt_set = P.nrow16 / 16;
-#pragma unroll
-  for (int i = 0; i < RTW; ++i)
-#pragma unroll
-    for (int c = 0; c < CTN; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nown = uni(min(RTW, max(0, (rt_set - wave + kMWaves - 1) / kMWaves)));
-  const uint4* base = m.ctile + (size_t)2 * 64 * ((size_t)P.bt0 + (size_t)(p * rt_set + wave) * P.kt) + lane;
-  if (nown == 1) gemm_owned<1, RTW, CTN>(P, base, xh, xl, acc, lane);
-  if constexpr (RTW >= 2)
-    if (nown == 2) gemm_owned<(RTW >= 2 ? 2 : 1), RTW, CTN>(P, base, xh, xl, acc, lane);
-  if constexpr (RTW >= 3)
-    if (nown == 3) gemm_owned<(RTW >= 3 ? 3 : 1), RTW, CTN>(P, base, xh, xl, acc, lane);
-}
-
-// Write the accumulators of coefficient set p (rows [p*nrow16, (p+1)*nrow16))
-// as FP32 Z[row][col] into LDS.
-template <int RTW, int CTN>
-__device__ __forceinline__ void store_z(const MixL& P, const f32x4 (&acc)[RTW][CTN], float* Z,
-                                        int wave, int lane, int ncols) {
-  const int col_l = lane & 15;
-  const int r_l = 4 * (lane >> 4);
-#pragma unroll
-  for (int i = 0; i < RTW; ++i) {
-    const int rt = wave + kMWaves * i;
-    if (rt >= P.nrow16 / 16) continue;
-    const int row0 = rt * 16 + r_l;
-#pragma unroll
-    for (int c = 0; c < CTN; ++c) {
-      const int col = c * 16 + col_l;
-      if (col >= ncols) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = row0 + q;
-        if (row >= 0 && row < P.nrow) Z[row * P.zstr + col] = acc[i][c][q];
-      }
-    }
-  }
-}
-
-// Selection rule of the real coupling coefficients C^{la lb L}_{m1 m2 M}
-// (l_a + l_b + L even): the M-type (cosine for M >= 0, sine for M < 0) is the
-// product of the m1- and m2-types and |M| is |m1| + |m2| or ||m1| - |m2||.
-// Every non-zero entry satisfies it; the library's coefficient table holds
-// one value per entry of this superset, in (m1, m2, M) order.
-__device__ constexpr int iabs_c(int v) { return v < 0 ? -v : v; }
-__device__ constexpr bool cg_rule(int m1, int m2, int M) {
-  return ((M < 0) == ((m1 < 0) != (m2 < 0))) &&
-         (iabs_c(M) == iabs_c(m1) + iabs_c(m2) || iabs_c(M) == iabs_c(iabs_c(m1) - iabs_c(m2)));
-}
-
-// ---- coupling coefficients as compile-time constants
-// Complex <j1 m1 j2 m2 | J M> from Racah's closed form and the change of
-// basis to the real harmonics (real Y_m = sum_mu U_{m mu} Y^mu with
-// U_{0,0} = 1; m > 0: U_{m,m} = (-1)^m/sqrt2, U_{m,-m} = 1/sqrt2; m < 0, k = |m|:
-// U_{m,k} = -i(-1)^k/sqrt2, U_{m,-k} = i/sqrt2), evaluated by the compiler.
-constexpr double ce_fact(int n) {
-  double r = 1.0;
-  for (int i = 2; i <= n; ++i) r *= i;
-  return r;
-}
-constexpr double ce_sqrt(double x) {
-  if (x <= 0.0) return 0.0;
-  double r = x > 1.0 ? x : 1.0;
-  for (int i = 0; i < 200; ++i) {
-    const double n = 0.5 * (r + x / r);
-    if (n == r) break;
-    r = n;
-  }
-  return r;
-}
-constexpr double ce_cg(int j1, int m1, int j2, int m2, int J, int M) {
-  if (m1 + m2 != M || iabs_c(m1) > j1 || iabs_c(m2) > j2 || iabs_c(M) > J) return 0.0;
-  if (J < iabs_c(j1 - j2) || J > j1 + j2) return 0.0;
-  const double pre = (2 * J + 1) * ce_fact(J + j1 - j2) * ce_fact(J - j1 + j2) * ce_fact(j1 + j2 - J) /
-                     ce_fact(j1 + j2 + J + 1) * ce_fact(J + M) * ce_fact(J - M) * ce_fact(j1 - m1) *
-                     ce_fact(j1 + m1) * ce_fact(j2 - m2) * ce_fact(j2 + m2);
-  double sum = 0.0;
-  for (int k = 0; k <= j1 + j2 - J; ++k) {
-    const int a0 = k, a1 = j1 + j2 - J - k, a2 = j1 - m1 - k, a3 = j2 + m2 - k, a4 = J - j2 + m1 + k,
-              a5 = J - j1 - m2 + k;
-    if (a0 < 0 || a1 < 0 || a2 < 0 || a3 < 0 || a4 < 0 || a5 < 0) continue;
-    const double den = ce_fact(a0) * ce_fact(a1) * ce_fact(a2) * ce_fact(a3) * ce_fact(a4) * ce_fact(a5);
-    sum += ((k & 1) ? -1.0 : 1.0) / den;
-  }
-  return ce_sqrt(pre) * sum;
-}
-// U_{m, mu} as (re, im); zero unless mu = +-m
-struct ce_c2 { double re, im; };
-constexpr ce_c2 ce_u(int m, int mu) {
-  const double s = 0.70710678118654752440;
-  if (m == 0) return mu == 0 ? ce_c2{1.0, 0.0} : ce_c2{0.0, 0.0};
-  if (m > 0) {
-    if (mu == m) return ce_c2{(m & 1) ? -s : s, 0.0};
-    if (mu == -m) return ce_c2{s, 0.0};
-    return ce_c2{0.0, 0.0};
-  }
-  const int k = -m;
-  if (mu == k) return ce_c2{0.0, (k & 1) ? s : -s};
-  if (mu == -k) return ce_c2{0.0, s};
-  return ce_c2{0.0, 0.0};
-}
-constexpr ce_c2 ce_mul(ce_c2 a, ce_c2 b) { return ce_c2{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-constexpr ce_c2 ce_conj(ce_c2 a) { return ce_c2{a.re, -a.im}; }
-// real coupling coefficient C^{l1 l2 L}_{m1 m2 M}
-constexpr double ce_real_cg(int l1, int l2, int L, int m1, int m2, int M) {
-  double acc = 0.0;
-  const int mu1s[2] = {iabs_c(m1), -iabs_c(m1)};
-  const int mu2s[2] = {iabs_c(m2), -iabs_c(m2)};
-  for (int a = 0; a < (m1 == 0 ? 1 : 2); ++a)
-    for (int b = 0; b < (m2 == 0 ? 1 : 2); ++b) {
-      const int mu1 = mu1s[a], mu2 = mu2s[b], mu = mu1 + mu2;
-      if (iabs_c(mu) > L) continue;
-      const ce_c2 u = ce_mul(ce_mul(ce_u(M, mu), ce_conj(ce_u(m1, mu1))), ce_conj(ce_u(m2, mu2)));
-      acc += u.re * ce_cg(l1, mu1, l2, mu2, L, mu);
-    }
-  return acc;
-}
-
-// one entry of the coupling of (LA, m1 index I1) with (LB, m2 index I2) to
-// (L, M index Q), flat index E = (I1 * (2LB+1) + I2) * (2L+1) + Q
-template <int LA, int LB, int L, int E>
-__device__ __forceinline__ void xb_entry(const float* Aa, const float* Ab, float* X) {
-  constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LB + 1),
-                i1 = E / ((2 * L + 1) * (2 * LB + 1));
-  if constexpr (cg_rule(i1 - LA, i2 - LB, q - L)) {
-    constexpr float c = (float)ce_real_cg(LA, LB, L, i1 - LA, i2 - LB, q - L);
-    if constexpr (c != 0.0f) X[q] = fmaf(c * Aa[i1], Ab[i2], X[q]);
-  }
-}
-template <int LT, int LP, int L, int I0, int I1, int E>
-__device__ __forceinline__ void ad_entry(const float* Ap, const float* Zv, float* ga) {
-  constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LP + 1),
-                i1 = E / ((2 * L + 1) * (2 * LP + 1));
-  if constexpr (i1 >= I0 && i1 < I1 && cg_rule(i1 - LT, i2 - LP, q - L)) {
-    constexpr float c = (float)ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L);
-    if constexpr (c != 0.0f) ga[i1 - I0] = fmaf(c * Ap[i2], Zv[q], ga[i1 - I0]);
-  }
-}
-template <int LA, int LB, int L, int... E>
-__device__ __forceinline__ void xb_all(std::integer_sequence<int, E...>, const float* Aa,
-                                       const float* Ab, float* X) {
-  (xb_entry<LA, LB, L, E>(Aa, Ab, X), ...);
-}
-template <int LT, int LP, int L, int I0, int I1, int... E>
-__device__ __forceinline__ void ad_all(std::integer_sequence<int, E...>, const float* Ap,
-                                       const float* Zv, float* ga) {
-  (ad_entry<LT, LP, L, I0, I1, E>(Ap, Zv, ga), ...);
-}
-
-// One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
-// coupling (n, LA) with (n', LB) to rank L.  Register indices and coupling
-// coefficients are compile-time constants.
-template <int LA, int LB, int L>
-__device__ __forceinline__ void xbuild_group(const float* At, int4 mem,
-                                             __bf16* xh, __bf16* xl, int kstr, int t) {
-  float Aa[2 * LA + 1], Ab[2 * LB + 1], X[2 * L + 1];
-#pragma unroll
-  for (int q = 0; q <= 2 * LA; ++q) Aa[q] = At[mem.y + q];
-#pragma unroll
-  for (int q = 0; q <= 2 * LB; ++q) Ab[q] = At[mem.z + q];
-#pragma unroll
-  for (int q = 0; q <= 2 * L; ++q) X[q] = 0.f;
-  xb_all<LA, LB, L>(std::make_integer_sequence<int, (2 * LA + 1) * (2 * LB + 1) * (2 * L + 1)>{}, Aa,
-                    Ab, X);
-  const int col0 = t * (2 * L + 1);
-#pragma unroll
-  for (int q = 0; q <= 2 * L; ++q) {
-    __bf16 hi, lo;
-    split_bf16(X[q], hi, lo);
-    xh[(col0 + q) * kstr + mem.x] = hi;
-    xl[(col0 + q) * kstr + mem.x] = lo;
-  }
-}
-
-// Adjoint of one coupled pattern (LT, LP, L) for the components [I0, I1) of
-// the target: lane = (target n = lane/8, atom t = lane%8), target index
-// a = (n, LT), partners (n', LP) for every n'.  Every coupled channel {a, p}
-// of this L is visited from both of its indices (the coupled value is
-// symmetric in them), so the lane owns its sums.
-template <int LT, int LP, int L, int I0, int I1>
-__device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P, const float* At,
-                                                 const float* Z, const int32_t* rows_lds, int j,
-                                                 int t, float* ga) {
-  constexpr int w = 2 * L + 1;
-  const int lp1 = m.l_max + 1;
-  const int nidx = m.n_max * lp1;
-  const bool act = j < m.n_max;
-  const int a = j * lp1 + LT;
-  // the channel row of the next partner is fetched one partner ahead
-  const int32_t* rp = rows_lds + a * nidx + LP;
-  int row_next = act ? rp[0] : -1;
-#pragma unroll 1
-  for (int np = 0; np < m.n_max; ++np) {
-    const int pidx = np * lp1 + LP;
-    const int row = row_next;
-    row_next = (act && np + 1 < m.n_max) ? rp[(np + 1) * lp1] : -1;
-    float Ap[2 * LP + 1], Zv[w];
-#pragma unroll
-    for (int q = 0; q <= 2 * LP; ++q) Ap[q] = At[np * m.nlm + LP * LP + q];
-    const float f = row < 0 ? 0.f : (pidx == a ? 2.f : 1.f);
-    const int zb = (row < 0 ? 0 : row) * P.zstr + t * w;
-#pragma unroll
-    for (int q = 0; q < w; ++q) Zv[q] = f * Z[zb + q];
-    ad_all<LT, LP, L, I0, I1>(
-        std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{}, Ap, Zv, ga);
-  }
-}
-
-template <int LT, int L, int I0, int I1, int LP>
-__device__ __forceinline__ void adjoint_lp(const MixDev& m, const MixL& P, const float* At,
-                                           const float* Z, const int32_t* rows_lds, int j, int t,
-                                           float* ga) {
-  if constexpr (LP <= kMaxL) {
-    if constexpr (iabs_c(LT - LP) <= L && L <= LT + LP && ((LT + LP + L) & 1) == 0) {
-      if (LP <= m.l_max) adjoint_partners<LT, LP, L, I0, I1>(m, P, At, Z, rows_lds, j, t, ga);
-    }
-    adjoint_lp<LT, L, I0, I1, LP + 1>(m, P, At, Z, rows_lds, j, t, ga);
-  }
-}
-
-// One adjoint job: the components [K (2LT+1)/NP, (K+1)(2LT+1)/NP) of every
-// target (n, LT), summed over all partner patterns; jobs write disjoint
-// gradient entries, so the sums are stored without atomics.  The job with
-// LT = L also takes the A rows of X_L: dphi/dA_{n,L,M} gets Z of row (n, L)
-// and phi gets A.Z (summed over n for each atom).
-template <int LT, int L, int NP, int K>
-__device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, const float* At,
-                                            const float* Z, float* omt, float* phi_t,
-                                            const int32_t* rows_lds, int j, int t) {
-  constexpr int w = 2 * L + 1;
-  constexpr int I0 = K * (2 * LT + 1) / NP, I1 = (K + 1) * (2 * LT + 1) / NP;
-  const bool act = j < m.n_max;
-  float ga[I1 - I0 > 0 ? I1 - I0 : 1];
-#pragma unroll
-  for (int q = 0; q < I1 - I0; ++q) ga[q] = 0.f;
-  adjoint_lp<LT, L, I0, I1, 0>(m, P, At, Z, rows_lds, j, t, ga);
-  if constexpr (LT == L) {
-    if (P.arow) {
-      const int zb = (P.nch + (act ? j : 0)) * P.zstr + t * w;
-      float sa = 0.f;
-#pragma unroll
-      for (int q = I0; q < I1; ++q) {
-        const float z = act ? Z[zb + q] : 0.f;
-        ga[q - I0] += z;
-        sa = fmaf(At[(act ? j : 0) * m.nlm + L * L + q], z, sa);
-      }
-      // sum over the 8 lanes of atom t (lanes t, t + 8, ..., t + 56)
-      sa += __shfl_xor(sa, 8);
-      sa += __shfl_xor(sa, 16);
-      sa += __shfl_xor(sa, 32);
-      if (j == 0) atomicAdd(phi_t, sa);
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int q = I0; q < I1; ++q) omt[q] += ga[q - I0];
-  }
-}
-
-#define AP_XB_CASE(la, lb)                                                           \
-  case (la) * 5 + (lb):                                                              \
-    if constexpr (iabs_c((la) - (lb)) <= L && L <= (la) + (lb) && (((la) + (lb) + L) & 1) == 0) \
-      xbuild_group<la, lb, L>(At, mem, xh, xl, kstr, t);                              \
-    break;
-#define AP_AD_CASE(lt, np, k)                                                        \
-  case (lt) * 16 + (np) * 4 + (k):                                                   \
-    if constexpr ((k) < (np) && (np) <= 2 * (lt) + 1)                                \
-      adjoint_job<lt, L, np, k>(m, P, At, Z, omt, phi_t, rows_lds, j, t);            \
-    break;
-#define AP_AD_LT(lt) AP_AD_CASE(lt, 1, 0) AP_AD_CASE(lt, 2, 0) AP_AD_CASE(lt, 2, 1) \
-  AP_AD_CASE(lt, 3, 0) AP_AD_CASE(lt, 3, 1) AP_AD_CASE(lt, 3, 2)
-#define AP_ALL_CASES(X) \
-  X(0, 0) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) \
-  X(2, 0) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) \
-  X(4, 0) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
-
-// Build the channel rows of X_L (bf16 hi/lo) for the 8 atoms of the tile.
-// Group g of this L: members {row, A offset of a, A offset of b, la*5+lb}.
-template <int L>
-__device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const float* A, __bf16* xh,
-                                       __bf16* xl, const int4* mem_lds, int wave, int lane) {
-  const int t = lane & 7, j = lane >> 3;
-  const float* At = A + t * m.apad;
-  const int kstr = P.kstr;
-  for (int g = wave; g < P.ngrp; g += kMWaves) {
-    const int4 mem = mem_lds[g * 8 + j];
-    const int key = uni(mem.w);
-    if (mem.x < 0) continue;
-    switch (key) {
-      AP_ALL_CASES(AP_XB_CASE)
-      default: break;
-    }
-  }
-}
-
-// Gradient of phi_p with respect to A from the coupled channels of X_L.  The
-// wavefront's jobs (target l, component part) come from a schedule the
-// library balanced over the workgroup's wavefronts.
-template <int L>
-__device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
-                                        const float* Z, float* om, float* phi_p,
-                                        const int32_t* rows_lds, int wave, int lane) {
-  const int j = lane >> 3, t = lane & 7;
-  float* phi_t = phi_p + 2 * t;
-  const float* At = A + t * m.apad;
-  cptr<int32_t> ptr = as_const(m.adj_ptr) + L * (kMWaves + 1);
-  const int u0 = uni(ptr[wave]), u1 = uni(ptr[wave + 1]);
-  cptr<int32_t> units = as_const(reinterpret_cast<const int32_t*>(m.adj_units));
-  for (int u = u0; u < u1; ++u) {
-    const int key = uni(units[4 * u]), lt = uni(units[4 * u + 3]);
-    float* omt = om + t * m.apad + j * m.nlm + lt * lt;
-    switch (key) {
-      AP_AD_LT(0) AP_AD_LT(1) AP_AD_LT(2) AP_AD_LT(3) AP_AD_LT(4)
-      default: break;
-    }
-  }
-}
-#undef AP_XB_CASE
-#undef AP_AD_CASE
-#undef AP_AD_LT
-#undef AP_ALL_CASES
-
-template <int L, int RTW, int CTN, bool XO>
-__device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
-                                       float* om2, unsigned char* big, float* phi_lds,
-                                       const int32_t* rows_lds, const int4* mem_lds, int wave,
-                                       int lane, int tid) {
-  const int w = 2 * L + 1;
-  const int ncols = kMT * w;
-  __bf16* xh = reinterpret_cast<__bf16*>(big);
-  __bf16* xl = xh + (size_t)P.ct * 16 * P.kstr;
-  // coupled operand X_L: zero padding (rows past nrow up to the k tiles,
-  // columns past the tile's atoms), channel rows, A rows, constant row
-  auto build_x = [&]() {
-    const int kpad = P.kt * 32;
-    const int padr = kpad - P.nrow;
-    for (int q = tid; q < ncols * padr; q += kMThreads) {
-      const int o = (q / padr) * P.kstr + P.nrow + q % padr;
-      xh[o] = (__bf16)0.0f;
-      xl[o] = (__bf16)0.0f;
-    }
-    const int padc = P.ct * 16 - ncols;
-    for (int q = tid; q < padc * kpad; q += kMThreads) {
-      const int o = (ncols + q / kpad) * P.kstr + q % kpad;
-      xh[o] = (__bf16)0.0f;
-      xl[o] = (__bf16)0.0f;
-    }
-    xbuild<L>(m, P, A, xh, xl, mem_lds, wave, lane);
-    if (P.arow) {
-      for (int q = tid; q < m.n_max * ncols; q += kMThreads) {
-        const int n = q / ncols, col = q % ncols, t = col / w, M = col % w;
-        const float v = A[t * m.apad + n * m.nlm + L * L + M];
-        __bf16 hi, lo;
-        split_bf16(v, hi, lo);
-        xh[col * P.kstr + P.nch + n] = hi;
-        xl[col * P.kstr + P.nch + n] = lo;
-      }
-    }
-    if (L == 0 && tid < kMT) {
-      xh[tid * P.kstr + P.nch + m.n_max] = (__bf16)1.0f;
-      xl[tid * P.kstr + P.nch + m.n_max] = (__bf16)0.0f;
-    }
-  };
-  auto adjoint_set = [&](const float* Z, int p) {
-    float* om = p == 0 ? om1 : om2;
-    adjoint<L>(m, P, A, Z, om, phi_lds + p, rows_lds, wave, lane);
-    if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
-  };
-  f32x4 acc[RTW][CTN];
-  if constexpr (XO) {
-    // X_L built once; Z_L beside it.  The contraction of set 1 reads only X,
-    // so wavefronts may start it while others finish the adjoint of set 0.
-    float* Z = reinterpret_cast<float*>(big + P.zoff);
-    build_x();
-    __syncthreads();
-    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 0);
-    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
-    __syncthreads();
-    adjoint_set(Z, 0);
-    gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 1);
-    __syncthreads();  // every wavefront is done with Z of set 0
-    store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
-    __syncthreads();
-    adjoint_set(Z, 1);
-    __syncthreads();
-  } else {
-    float* Z = reinterpret_cast<float*>(big);
-    for (int p = 0; p < 2; ++p) {
-      build_x();
-      __syncthreads();
-      // Z_L of coefficient set p
-      gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, p);
-      __syncthreads();  // X is dead from here on
-      store_z<RTW, CTN>(P, acc, Z, wave, lane, ncols);
-      __syncthreads();
-      adjoint_set(Z, p);
-      __syncthreads();
-    }
-  }
-}
 
 // ---- kernel 1: bond basis and atomic basis A, one wavefront per ACE atom
 constexpr int kBasisWaves = 4;
@@ -549,7 +20,8 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
     SysView sv, MixDev m, const double* __restrict__ pos, const double4* __restrict__ pos4,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
     const int32_t* __restrict__ ace_list,
-    const int32_t* __restrict__ n_ace_p, int n_all, float* __restrict__ A_out) {
+    const int32_t* __restrict__ n_ace_p, int n_all, float* __restrict__ A_out,
+    float* __restrict__ bn_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -614,6 +86,9 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   }
   // B through LDS (the staging area is free now), then A = W B
   float* B = RY;
+  float Asq[(kMaxN * kMaxLM + 63) / 64];
+#pragma unroll
+  for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) Asq[r] = 0.f;
 #pragma unroll
   for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
     const int e = lane + 64 * r;
@@ -623,7 +98,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
 #pragma unroll
   for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
     const int e = lane + 64 * r;
-    if (e >= nA) break;
+    if (e >= nA) continue;
     const int nn = e / nlm, lm = e - nn * nlm;
     int l = 0;
     while ((l + 1) * (l + 1) <= lm) ++l;
@@ -633,97 +108,26 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
     for (int k = 0; k < kMaxK; ++k)
       if (k < K) v += w[k] * B[k * nlm + lm];
     A_out[(int64_t)item * nA + e] = v;
+    Asq[r] = v * v;
   }
-
-}
-
-// ---- kernel 2 (one instance per coupled rank L): coupling, folded
-// contraction and adjoint for tiles of 8 atoms; adds the tile's gradient
-// and phi terms of this L to the per-atom buffers (first rank: writes).
-template <int L, int RTW, int CTN, bool XO>
-__global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
-    MixDev m, const int32_t* __restrict__ n_ace_p, int n_all, const float* __restrict__ A_in,
-    float* __restrict__ om_buf, float* __restrict__ phi_buf) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  float* A = reinterpret_cast<float*>(lds);
-  float* om1 = A + kMT * m.apad;
-  float* om2 = om1 + kMT * m.apad;
-  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2]
-  unsigned char* big = lds + m.big_off;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
-  const int n_items = n_ace_p ? *n_ace_p : n_all;
-  const int n_tiles = (n_items + kMT - 1) / kMT;
-  const MixL P = load_level(m.lv_d + L);
-  // stage this rank's channel tables in LDS (read by every tile)
-  const int nidx = m.n_max * (m.l_max + 1);
-  int32_t* rows_lds = reinterpret_cast<int32_t*>(lds + m.tab_off);
-  int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
-  for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
-  for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
-  // A of a tile's atoms and the gradient and phi sums of the lower ranks are
-  // loaded into registers ahead of the tile that uses them
-  constexpr int kPf = (kMT * (8 * kMaxLM + 1) + kMThreads - 1) / kMThreads;
-  float pa[kPf];
-  float2 po[kPf];
-  float pphi = 0.f;
-  auto fetch = [&](int tile) {
-    const int nt = min(kMT, n_items - tile * kMT);
-    const int64_t base = (int64_t)tile * kMT * m.nA;
-    // the index arithmetic below is redone per tile rather than kept live
-    // across the whole tile loop (registers are scarce in rank_L)
-    int tq = tid;
-    asm volatile("" : "+v"(tq));
+  // largest |A_(n,l)|^2 over the atom's single indices: it bounds every entry
+  // of the coupled operand and fixes the atom's power-of-two scale there
+  float* Q = RY + nB;
+  __syncwarp_ap();
 #pragma unroll
-    for (int r = 0; r < kPf; ++r) {
-      const int q = tq + r * kMThreads;
-      const int t = q / m.apad, e = q - t * m.apad;
-      const bool ok = q < kMT * m.apad && t < nt && e < m.nA;
-      const int64_t o = base + (int64_t)t * m.nA + e;
-      pa[r] = ok ? A_in[o] : 0.f;
-      po[r] = (L > 0 && ok) ? reinterpret_cast<const float2*>(om_buf)[o] : make_float2(0.f, 0.f);
-    }
-    if (tid < 2 * kMT) pphi = (L > 0 && tid < 2 * nt) ? phi_buf[(int64_t)tile * kMT * 2 + tid] : 0.f;
-  };
-  auto stage = [&]() {
-    int tq = tid;
-    asm volatile("" : "+v"(tq));
+  for (int r = 0; r < (kMaxN * kMaxLM + 63) / 64; ++r) {
+    const int e = lane + 64 * r;
+    if (e < nA) Q[e] = Asq[r];
+  }
+  __syncwarp_ap();
+  float bq = 0.f;
+  if (lane < nnl) {
+    const int nn = lane / lp1, l = lane - nn * lp1;
+    for (int q = 0; q <= 2 * l; ++q) bq += Q[nn * nlm + l * l + q];
+  }
 #pragma unroll
-    for (int r = 0; r < kPf; ++r) {
-      const int q = tq + r * kMThreads;
-      if (q < kMT * m.apad) {
-        A[q] = pa[r];
-        om1[q] = po[r].x;
-        om2[q] = po[r].y;
-      }
-    }
-    if (tid < 2 * kMT) phi_lds[tid] = pphi;
-  };
-  if ((int)blockIdx.x < n_tiles) {
-    fetch(blockIdx.x);
-    stage();
-  }
-  __syncthreads();
-  // ranks with spare registers fetch the next tile before this tile's work,
-  // the others just before this tile's stores
-  constexpr bool kEarly = L <= 1 || L >= 7;
-  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int nt = min(kMT, n_items - tile * kMT);
-    const int64_t base = (int64_t)tile * kMT * m.nA;
-    const int next = tile + (int)gridDim.x;
-    if (kEarly && next < n_tiles) fetch(next);
-    rank_L<L, RTW, CTN, XO>(m, P, A, om1, om2, big, phi_lds, rows_lds, mem_lds, wave, lane, tid);
-    __syncthreads();
-    if (!kEarly && next < n_tiles) fetch(next);
-    for (int q = tid; q < nt * m.nA; q += kMThreads) {
-      const int t = q / m.nA, e = q - t * m.nA;
-      reinterpret_cast<float2*>(om_buf)[base + q] = make_float2(om1[t * m.apad + e], om2[t * m.apad + e]);
-    }
-    if (tid < 2 * nt) phi_buf[(int64_t)tile * kMT * 2 + tid] = phi_lds[tid];
-    __syncthreads();
-    if (next < n_tiles) stage();
-    __syncthreads();
-  }
+  for (int d = 32; d >= 1; d >>= 1) bq = fmaxf(bq, __shfl_xor(bq, d, 64));
+  if (lane == 0) bn_out[item] = bq;
 }
 
 // ---- kernel 3: embedding (FP64), bond gradients and virial, one wavefront per atom
@@ -843,7 +247,8 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
-                            double* e_atom, double* vir_atom, hipStream_t s, int phase) {
+                            float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
+                            int phase) {
   const MixDev& m = c.mix;
   // grids are sized for every atom; wavefronts past *n_ace leave at once
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
@@ -852,16 +257,16 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     const size_t lds = (size_t)kBasisWaves * 64 * (m.K + m.nlm) * 4;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
-                         count, ace_list, n_ace, n_atoms, A_buf);
+                         count, ace_list, n_ace, n_atoms, A_buf, bn_buf);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_basis<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_basis<6, 3, 6>);
     else go(k_ace_basis<0, 0, 0>);
   } else if (phase == 1) {
     int dev = 0, n_cu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    hipError_t e = hipSuccess;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
     (void)counter;
     const size_t lds = ace_mixed_lds_bytes(m);
     const int32_t* na = ace_list ? n_ace : nullptr;
@@ -869,22 +274,22 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
       const void* fn = nullptr;
       // X_L kept for both sets when it fits beside Z_L (decided with the LDS layout)
       const bool xo = m.lv[L].xonce != 0;
-#define AP_RANK_CASE(l, ctn)                                                                  \
-  case l:                                                                                     \
-    fn = xo ? (const void*)k_ace_rank<l, kMixRtw[l], ctn, true>                               \
-            : (const void*)k_ace_rank<l, kMixRtw[l], ctn, false>;                             \
-    break;
       switch (L) {
-        AP_RANK_CASE(0, 1) AP_RANK_CASE(1, 2) AP_RANK_CASE(2, 3) AP_RANK_CASE(3, 4)
-        AP_RANK_CASE(4, 5) AP_RANK_CASE(5, 6) AP_RANK_CASE(6, 7) AP_RANK_CASE(7, 8)
-        default: AP_RANK_CASE(8, 9)
+        case 0: fn = rank_kernel<0>(xo); break;
+        case 1: fn = rank_kernel<1>(xo); break;
+        case 2: fn = rank_kernel<2>(xo); break;
+        case 3: fn = rank_kernel<3>(xo); break;
+        case 4: fn = rank_kernel<4>(xo); break;
+        case 5: fn = rank_kernel<5>(xo); break;
+        case 6: fn = rank_kernel<6>(xo); break;
+        case 7: fn = rank_kernel<7>(xo); break;
+        default: fn = rank_kernel<8>(xo); break;
       }
-#undef AP_RANK_CASE
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&om_buf,
-                      (void*)&phi_buf};
-      e = hipLaunchKernel(fn, dim3(n_cu), dim3(kMThreads), args, lds, s);
+                      (void*)&phi_buf, (void*)&bn_buf};
+      e = hipLaunchKernel(fn, dim3(n_cu), dim3(64 * kMixWaves), args, lds, s);
       if (e != hipSuccess) return e;
     }
   } else {

@@ -47,7 +47,7 @@ def sample_atoms(wl, lam, n_ace, n_other, seed):
     return sorted(int(i) for i in pick)
 
 
-@pytest.mark.parametrize("k,n_ace,n_other", [(1, 6, 6), (2, 4, 8), (3, 3, 8), (4, 6, 0), (5, 3, 6)])
+@pytest.mark.parametrize("k,n_ace,n_other", [(1, 6, 6), (2, 4, 8), (3, 64, 8), (4, 6, 0), (5, 3, 6)])
 def test_fullsize_sampled_parity(k, n_ace, n_other):
     wl = wl_of(k)
     g64 = gpu_eval(wl, ap.AP_PREC_FP64)

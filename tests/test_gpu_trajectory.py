@@ -1,8 +1,7 @@
 """200 velocity-Verlet steps of the 108,000-atom Cu-like indentation slab
-(moving indenter) on the FP64 path; at steps 0, 50, 100 and 150 the mixed
-path evaluated at the same positions (and indenter position) stays within
-1e-5 relative force error, at step 200 within 2e-5 (atoms at the embedding
-kink, see below), and the FP64 trajectory stays finite."""
+(moving indenter) on the FP64 path; at steps 0, 50, 100, 150 and 200 the
+mixed path evaluated at the same positions (and indenter position) stays
+within 1e-5 relative force error, and the FP64 trajectory stays finite."""
 import numpy as np
 import pytest
 import torch
@@ -37,14 +36,7 @@ def test_fp64_trajectory_mixed_forces_along_it():
         errs.append(e)
         print(f"step {step}: n_ace {int(st.n_ace.item())}, max|F| {float(st.force.abs().max()):.3f}, "
               f"mixed force rel err {e:.2e}, indenter z {st.c.ind_centre[2]:.4f}")
-    assert all(np.isfinite(errs)) and max(errs[:4]) <= 1e-5
-    # By step 200 a few ACE atoms sit at the kink of the embedding
-    # sqrt(|phi2| + 1e-6) (E^ACE ~ 1e-3): there dE/dphi2 ~ 500 and its
-    # derivative ~ 1e8 amplify the ~1e-6 absolute error of the split-bf16
-    # phi2, so those atoms' ACE forces differ by up to ~5e-3 eV/A (the ACE-only
-    # error rises to ~1e-3 while every other atom stays at the 1e-6 level).
-    # The total error measured there is 1.4e-5.
-    assert errs[4] <= 2e-5
+    assert all(np.isfinite(errs)) and max(errs) <= 1e-5
     # the indenter moved by 200 dt v
     z0 = float(wl.indenter["centre"][2])
     assert abs((z0 - st.c.ind_centre[2]) - 200 * wl.dt * float(-wl.indenter["vel"][2])) < 1e-9
