@@ -201,6 +201,21 @@ ap_status ap_blend(ap_ctx* ctx, const ap_systems* sys, const double* pos,
                    const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                    int32_t* n_ace, void* stream);
 
+/* ap_blend for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as ap_blend; it allocates nothing and
+ * uploads nothing.  Its per-atom flags and the compaction's partial sums live
+ * in a static device array of the library (one copy per GPU, about 16 MB,
+ * held until the process ends), so n_atoms <= AP_BLEND_NOALLOC_MAX_ATOMS
+ * (larger systems: AP_ERR_ARG, nothing enqueued).  The context's device must
+ * be current (else AP_ERR_ARG).  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams or host threads) race;
+ * calls ordered on one stream do not. */
+#define AP_BLEND_NOALLOC_MAX_ATOMS 4000000
+ap_status ap_blend_noalloc(ap_ctx* ctx, const ap_systems* sys, const double* pos,
+                           const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
+                           int32_t* n_ace, void* stream);
+
 /* EAM part weighted by w_i = 1 - lambda_i (lambda NULL: w = 1).
  * e_atom[i] = w_i E_i^EAM; force = -dE/dr of sum_i w_i E_i^EAM;
  * virial[s*9 + 3a + b] = -sum_{i in s} sum_j d_ij,a G_ij,b (NULL: skipped). */

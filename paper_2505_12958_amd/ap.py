@@ -95,6 +95,8 @@ def lib():
         L.ap_build_neighbors.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList),
                                          C.POINTER(i32), vp]
         L.ap_blend.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(LambdaRule), vp, vp, vp, vp]
+        L.ap_blend_noalloc.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(LambdaRule), vp, vp,
+                                       vp, vp]
         L.ap_eam_forces.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList), vp, vp, vp, vp,
                                     C.c_uint32, vp]
         L.ap_ace_forces.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList), vp, vp, vp, vp, vp,
@@ -107,7 +109,7 @@ def lib():
         L.ap_profile.argtypes = [vp, i32]
         L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
         L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
-        for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend",
+        for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_blend_noalloc",
                   "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -115,6 +117,7 @@ def lib():
 
 
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
+           "ap_blend_noalloc",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
            "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
 PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce",
@@ -262,6 +265,12 @@ class Context:
         r = rule_struct(rule, mask)
         st = lib().ap_blend(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
                             _ptr(ace_list), _ptr(n_ace), _stream())
+        self._check(st)
+
+    def blend_noalloc(self, sysarg, pos, rule, lam, ace_list, n_ace, mask=None):
+        r = rule_struct(rule, mask)
+        st = lib().ap_blend_noalloc(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
+                                    _ptr(ace_list), _ptr(n_ace), _stream())
         self._check(st)
 
     def eam_forces(self, sysarg, pos, nl, lam, e_atom, force, virial=None, accumulate=False):

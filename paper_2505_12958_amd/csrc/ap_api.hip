@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 
 #include "ap_internal.h"
@@ -16,6 +17,24 @@
 namespace ap {
 
 static thread_local std::string g_create_err;
+
+// --------------------------------------------------------------------------
+// Static device scratch of the entry point that allocates nothing
+// (ap_blend_noalloc): the per-atom flags of the switching pass and the
+// partial sums of the compaction scan.  Every GPU the library runs on holds
+// its own copy of this array until the process ends.  In host code the name
+// only stands in for the device symbol; host code uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device when the first context on that device is created.
+constexpr int64_t kNoallocMaxAtoms = AP_BLEND_NOALLOC_MAX_ATOMS;
+constexpr size_t kNoallocFlagBytes = (size_t)4 * kNoallocMaxAtoms;            // int32 per atom
+constexpr size_t kNoallocScanBytes = (size_t)4 * (kNoallocMaxAtoms / 4096 + 2);  // scan partial sums
+constexpr size_t kStaticScratchBytes = kNoallocFlagBytes + 256 + kNoallocScanBytes;
+static_assert(kNoallocFlagBytes % 256 == 0, "scan sums start 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
 
 ap_status fail(Ctx* ctx, ap_status s, const std::string& msg) {
   if (ctx) ctx->err = msg; else g_create_err = msg;
@@ -781,6 +800,22 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   return AP_OK;
 }
 
+// Address of `scratch` on the context's device (current when called).
+static ap_status static_scratch(Ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fail(ctx, AP_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    if (!p) return fail(ctx, AP_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[ctx->device] = p;
+  }
+  ctx->static_scratch = g_scratch_ptr[ctx->device];
+  return AP_OK;
+}
+
 static ap_status upload_table(Ctx* ctx, const ap_table& t, TableDev* d, const char* name) {
   if (t.n_knots < 2 || !(t.dx > 0) || !t.coef)
     return fail(ctx, AP_ERR_ARG, std::string("invalid EAM table ") + name);
@@ -830,7 +865,12 @@ ap_status ap_create(ap_ctx** out, int32_t device, int32_t precision, const ap_ea
   Ctx* ctx = new Ctx();
   ctx->device = device;
   ctx->precision = precision;
-  ap_status st = AP_OK;
+  ap_status st = static_scratch(ctx);
+  if (st != AP_OK) {
+    g_create_err = ctx->err;
+    ap_destroy((ap_ctx*)ctx);
+    return st;
+  }
   if (eam) {
     if ((st = upload_table(ctx, eam->phi, &ctx->phi, "phi")) ||
         (st = upload_table(ctx, eam->rho, &ctx->rho, "rho")) ||
@@ -1119,6 +1159,41 @@ ap_status ap_indenter(ap_ctx* c, const ap_systems* sys, const double* pos, const
     if (e_ind) AP_HIP(hipMemcpyAsync(e_ind, out, 8, hipMemcpyDeviceToDevice, s));
     if (load) AP_HIP(hipMemcpyAsync(load, out + 1, 8, hipMemcpyDeviceToDevice, s));
   }
+  return AP_OK;
+}
+
+ap_status ap_blend_noalloc(ap_ctx* c, const ap_systems* sys, const double* pos,
+                           const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
+                           int32_t* n_ace, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if ((st = check_blend_args(ctx, rule, lambda, ace_list, n_ace))) return st;
+  // the systems are only validated: the switching pass needs no geometry, so
+  // nothing is uploaded (the systems cache of the other calls may allocate)
+  if (!sys || !sys->sys_offset || sys->n_systems < 1 || sys->n_systems > kMaxSys)
+    return fail(ctx, AP_ERR_ARG, "sys is NULL or has no systems");
+  const int64_t N = sys->n_atoms;
+  if (N < 0 || sys->sys_offset[0] != 0 || sys->sys_offset[sys->n_systems] != N)
+    return fail(ctx, AP_ERR_ARG, "sys_offset must run from 0 to n_atoms");
+  if (N > kNoallocMaxAtoms) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "ap_blend_noalloc: %lld atoms exceed its static scratch (at most %lld)",
+             (long long)N, (long long)kNoallocMaxAtoms);
+    return fail(ctx, AP_ERR_ARG, buf);
+  }
+  if (!pos && N > 0) return fail(ctx, AP_ERR_ARG, "pos is NULL");
+  int cur = -1;
+  AP_HIP(hipGetDevice(&cur));
+  if (cur != ctx->device) return fail(ctx, AP_ERR_ARG, "ap_blend_noalloc: the context's device is not current");
+  if (!ctx->static_scratch) return fail(ctx, AP_ERR_HIP, "static scratch address not set up");
+  // flags [0, 4 N) and the scan's partial sums: both written before they are
+  // read, so nothing is cleared; no timer events (creating one may allocate)
+  int32_t* flag = (int32_t*)ctx->static_scratch;
+  int32_t* tmp = (int32_t*)((unsigned char*)ctx->static_scratch + kNoallocFlagBytes + 256);
+  AP_HIP(launch_blend((int32_t)N, pos, *rule, lambda, flag, s));
+  AP_HIP(launch_compact((int32_t)N, flag, ace_list, n_ace, tmp, s));
   return AP_OK;
 }
 

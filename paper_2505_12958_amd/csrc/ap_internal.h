@@ -172,6 +172,7 @@ struct Ctx {
   Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
+  void* static_scratch = nullptr;      // this device's address of the static scratch array
   size_t ace_lds = 0;
   // algorithmic work counts (ap_info)
   double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
