@@ -372,6 +372,9 @@ def main():
                      "frac": a_mfma / PEAK["f16_mfma"], "flops_per_pass": f_mfma,
                      "executed_flops_per_pass": ctx.info("ace.mfma_flops_atom") * n_ace},
             "t_roof_ms": t_roof_rank * 1e3, "t_roof_frac": t_roof_rank / t_rank,
+            "launch_mode": ["one kernel per coupled rank", "all ranks in one persistent launch",
+                            "all ranks in one persistent launch, device work counter"][
+                int(ctx.info("ace.rank_mode"))],
         }
     roof["step"] = {"t_roof_ms": t_roof_step * 1e3, "ms_per_step": dt / args.steps * 1e3,
                     "frac": t_roof_step / (dt / args.steps),

@@ -7,7 +7,10 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -800,6 +803,76 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   return AP_OK;
 }
 
+// --------------------------------------------------------------------------
+// Launch-mode tuner of the mixed rank phase.  The three modes (one kernel per
+// coupled rank; all ranks in one persistent launch, tiles round-robin; the
+// same with a device work counter) are timed with HIP events on the first
+// call of a context for each bucket of the atom count (powers of two), on that
+// call's own inputs, and the fastest is kept.  AP_RANK_MODE=0/1/2 forces a
+// mode; AP_AUTOTUNE=0 turns the tuner off (mode 1); AP_AUTOTUNE_CACHE names a
+// JSON file {"<device>|<model shape>|b<bucket>": mode, ...} that is read when
+// a context is created and updated after each tuning.
+static int size_bucket(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= std::max<int64_t>(n, 1)) ++b;
+  return b;
+}
+
+static std::map<std::string, int> read_tune_cache(const std::string& path) {
+  std::map<std::string, int> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('"');
+    if (a == std::string::npos) continue;
+    const size_t b = line.find('"', a + 1);
+    const size_t c = b == std::string::npos ? b : line.find(':', b);
+    if (c == std::string::npos) continue;
+    char* end = nullptr;
+    const long v = std::strtol(line.c_str() + c + 1, &end, 10);
+    if (end != line.c_str() + c + 1) out[line.substr(a + 1, b - a - 1)] = (int)v;
+  }
+  return out;
+}
+
+static void write_tune_cache(const std::string& path, const std::string& key, int mode) {
+  std::map<std::string, int> all = read_tune_cache(path);
+  all[key] = mode;
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return;
+    f << "{\n";
+    size_t k = 0;
+    for (auto& kv : all) f << "  \"" << kv.first << "\": " << kv.second << (++k < all.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+static void setup_tuner(Ctx* ctx, const ap_ace_model* m) {
+  hipDeviceProp_t prop;
+  std::string dev = "hip";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) dev = std::string(prop.gcnArchName) + " " + prop.name;
+  std::ostringstream k;
+  k << dev << "|ace " << m->n_max << " " << m->l_max << " " << m->K << " " << m->nu_max << " "
+    << ctx->ace.L_max << " " << m->n_funcs;
+  ctx->tune_key = k.str();
+  if (const char* f = std::getenv("AP_RANK_MODE")) {
+    const int v = std::atoi(f);
+    if (v >= 0 && v < AP_RANK_N_MODES) ctx->rank_mode_forced = v;
+  }
+  if (const char* f = std::getenv("AP_AUTOTUNE"))
+    if (std::string(f) == "0" && ctx->rank_mode_forced < 0) ctx->rank_mode_forced = AP_RANK_FUSED;
+  if (const char* f = std::getenv("AP_AUTOTUNE_CACHE")) {
+    ctx->tune_cache = f;
+    const std::string pre = ctx->tune_key + "|b";
+    for (auto& kv : read_tune_cache(ctx->tune_cache))
+      if (kv.first.compare(0, pre.size(), pre) == 0 && kv.second >= 0 && kv.second < AP_RANK_N_MODES)
+        ctx->rank_mode_tuned[std::atoi(kv.first.c_str() + pre.size())] = kv.second;
+  }
+}
+
 // Address of `scratch` on the context's device (current when called).
 static ap_status static_scratch(Ctx* ctx) {
   if (ctx->device < 0 || ctx->device >= kMaxDevices)
@@ -888,6 +961,7 @@ ap_status ap_create(ap_ctx** out, int32_t device, int32_t precision, const ap_ea
       return st;
     }
     ctx->has_ace = true;
+    setup_tuner(ctx, ace);
   }
   if ((st = ensure(ctx, ctx->flags, 64)) != AP_OK) {
     g_create_err = ctx->err;
@@ -1093,12 +1167,66 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
         (st = ensure(ctx, ctx->mix_om, 8 * rows * mx.nA)) ||
         (st = ensure(ctx, ctx->mix_phi, 8 * rows)) || (st = ensure(ctx, ctx->mix_bn, 4 * rows)))
       return st;
-    for (int phase = 0; phase < 3; ++phase) {
-      PhaseTimer timer(ctx, phase == 1 ? AP_PHASE_ACE : AP_PHASE_ACE_BOND, s);
-      AP_HIP(launch_ace_mixed(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count,
-                              nl->capacity, (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p,
-                              (float*)ctx->mix_A.p, (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p,
-                              (float*)ctx->mix_bn.p, e_atom, vir, s, phase));
+    auto phase_run = [&](int phase, int mode) -> hipError_t {
+      if (phase == 1 && mode == AP_RANK_FUSED_QUEUE) {
+        const hipError_t e = launch_ace_reset((int32_t*)ctx->ace_counter.p, s);
+        if (e != hipSuccess) return e;
+      }
+      return launch_ace_mixed(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count,
+                              nl->capacity, (int32_t)N, lambda, ace_list, n_ace,
+                              (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p, (float*)ctx->mix_A.p,
+                              (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p, (float*)ctx->mix_bn.p, e_atom,
+                              vir, s, phase, mode);
+    };
+    {
+      PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
+      AP_HIP(phase_run(0, 0));
+    }
+    int mode = ctx->rank_mode_forced;
+    if (mode > AP_RANK_PER_L && !rank_kernel_fused(false, rank_xomask(ctx->mix), ctx->mix.L_max))
+      mode = AP_RANK_PER_L;
+    if (mode < 0) {
+      const int bucket = size_bucket(N);
+      auto it = ctx->rank_mode_tuned.find(bucket);
+      if (it != ctx->rank_mode_tuned.end()) {
+        mode = it->second;
+      } else {
+        // time every mode twice on these inputs (the first round warms up);
+        // each run rewrites the phase's outputs completely
+        // (the fused modes exist for the rank layouts with an instance)
+        const int n_modes = rank_kernel_fused(false, rank_xomask(ctx->mix), ctx->mix.L_max) ? AP_RANK_N_MODES : 1;
+        hipEvent_t ev[2 * AP_RANK_N_MODES];
+        for (auto& e : ev) AP_HIP(hipEventCreate(&e));
+        for (int rep = 0; rep < 2; ++rep)
+          for (int md = 0; md < n_modes; ++md) {
+            if (rep == 1) AP_HIP(hipEventRecord(ev[2 * md], s));
+            AP_HIP(phase_run(1, md));
+            if (rep == 1) AP_HIP(hipEventRecord(ev[2 * md + 1], s));
+          }
+        AP_HIP(hipEventSynchronize(ev[2 * n_modes - 1]));
+        float best = 0.f;
+        for (int md = 0; md < n_modes; ++md) {
+          float ms = 0.f;
+          AP_HIP(hipEventElapsedTime(&ms, ev[2 * md], ev[2 * md + 1]));
+          if (mode < 0 || ms < best) {
+            best = ms;
+            mode = md;
+          }
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        ctx->rank_mode_tuned[bucket] = mode;
+        if (!ctx->tune_cache.empty())
+          write_tune_cache(ctx->tune_cache, ctx->tune_key + "|b" + std::to_string(bucket), mode);
+      }
+    }
+    ctx->last_rank_mode = mode;
+    {
+      PhaseTimer timer(ctx, AP_PHASE_ACE, s);
+      AP_HIP(phase_run(1, mode));
+    }
+    {
+      PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
+      AP_HIP(phase_run(2, 0));
     }
   }
   {
@@ -1351,6 +1479,7 @@ ap_status ap_info(const ap_ctx* c, const char* key, double* value) {
   else if (k == "eam.flops_bond") *value = 80.0;
   else if (k == "ace.mfma_tiles") *value = ctx->mix_tiles;
   else if (k == "ace.mfma_flops_atom") *value = ctx->mix_mfma_flops;
+  else if (k == "ace.rank_mode") *value = ctx->last_rank_mode;
   else return fail(const_cast<Ctx*>(ctx), AP_ERR_ARG, "unknown info key");
   return AP_OK;
 }

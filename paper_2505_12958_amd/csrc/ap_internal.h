@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -98,6 +99,10 @@ struct CgEnt {
 // (row tile rt = wave + kMixWaves * i).
 constexpr int kMixWaves = 8;
 constexpr int kMixRtw[2 * kMaxL + 1] = {2, 3, 3, 3, 3, 2, 2, 1, 1};
+// launch modes of the rank phase: one kernel per coupled rank; all ranks in
+// one persistent launch with tiles round-robin; the same with tiles from a
+// device work counter
+enum { AP_RANK_PER_L = 0, AP_RANK_FUSED = 1, AP_RANK_FUSED_QUEUE = 2, AP_RANK_N_MODES = 3 };
 
 struct MixL {
   int32_t nrow, nrow16, nch, arow;  // rows of X_L, padded to 16, channel rows, has A rows
@@ -173,6 +178,14 @@ struct Ctx {
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
   void* static_scratch = nullptr;      // this device's address of the static scratch array
+  // launch mode of the mixed rank phase: forced (AP_RANK_MODE, >= 0) or tuned
+  // per bucket of the atom count (timed on first use, optionally cached in
+  // the JSON file named by AP_AUTOTUNE_CACHE)
+  int rank_mode_forced = -1;
+  std::map<int, int> rank_mode_tuned;
+  std::string tune_key;                 // device and model shape, prefix of the cache keys
+  std::string tune_cache;               // cache file path ("" = none)
+  int last_rank_mode = -1;
   size_t ace_lds = 0;
   // algorithmic work counts (ap_info)
   double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
@@ -275,12 +288,18 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase);
+                            int phase, int rank_mode = AP_RANK_FUSED);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 // the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
 // per L); xo: the variant that keeps X_L in LDS for both coefficient sets
 template <int L>
 const void* rank_kernel(bool xo);
+// all coupled ranks in one persistent launch (k_ace_rank_fused.hip) for the
+// rank layout (bit L of xomask: X_L kept for both sets; lmax: largest rank),
+// or NULL when no instance exists for that layout; queue: tiles from the
+// device work counter instead of round-robin
+const void* rank_kernel_fused(bool queue, uint32_t xomask, int lmax);
+uint32_t rank_xomask(const MixDev& m);
 hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
                           int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s);

@@ -11,7 +11,8 @@ PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libap.so")
 OBJ = os.path.join(PKG, "_build")
 
-SOURCES = ["ap_api.hip", "k_nbr.hip", "k_misc.hip", "k_eam.hip", "k_ace.hip", "k_ace_mixed.hip"]
+SOURCES = ["ap_api.hip", "k_nbr.hip", "k_misc.hip", "k_eam.hip", "k_ace.hip", "k_ace_mixed.hip",
+           "k_ace_rank_fused.hip"]
 # (source, object name, extra flags): the mixed rank kernels are compiled once
 # per coupled rank L, in parallel
 UNITS = [(s, s.replace(".hip", ""), []) for s in SOURCES] + [

@@ -242,13 +242,20 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
 
 size_t ace_mixed_lds_bytes(const MixDev& m) { return m.big_off + m.big_bytes; }
 
+uint32_t rank_xomask(const MixDev& m) {
+  uint32_t x = 0;
+  for (int L = 0; L <= m.L_max; ++L)
+    if (m.lv[L].xonce) x |= 1u << L;
+  return x;
+}
+
 hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
                             const int32_t* nbr,
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase) {
+                            int phase, int rank_mode) {
   const MixDev& m = c.mix;
   // grids are sized for every atom; wavefronts past *n_ace leave at once
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
@@ -267,9 +274,21 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    (void)counter;
     const size_t lds = ace_mixed_lds_bytes(m);
     const int32_t* na = ace_list ? n_ace : nullptr;
+    if (rank_mode != AP_RANK_PER_L) {
+      // one persistent launch over all coupled ranks; the work counter was
+      // reset on the stream before this phase
+      const void* fn = rank_kernel_fused(rank_mode == AP_RANK_FUSED_QUEUE, rank_xomask(m), m.L_max);
+      if (!fn) return hipErrorInvalidDeviceFunction;
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      void* args[] = {(void*)&m, (void*)&na, (void*)&n_atoms, (void*)&A_buf, (void*)&om_buf,
+                      (void*)&phi_buf, (void*)&bn_buf, (void*)&counter};
+      e = hipLaunchKernel(fn, dim3(n_cu), dim3(64 * kMixWaves), args, lds, s);
+      if (e != hipSuccess) return e;
+      return hipGetLastError();
+    }
     for (int L = 0; L <= m.L_max; ++L) {
       const void* fn = nullptr;
       // X_L kept for both sets when it fits beside Z_L (decided with the LDS layout)
