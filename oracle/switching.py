@@ -46,3 +46,139 @@ def lambda_of(pos, rule):
 def ace_list(lam):
     """Indices with lambda > 0, ascending."""
     return np.nonzero(np.asarray(lam) > 0.0)[0]
+
+
+# ---------------------------------------------------------------------------
+# Dynamic switching (section "Adaptive-precision potential" and the appendix
+# "Switching function" with the table of the adaptive-precision model's
+# parameters).  The paper takes the detection from the centro-symmetry
+# parameter (CSP) of the 14 nearest neighbours, averaged over time, maps it
+# to the switching parameter between CSP_lo and CSP_hi, spreads the precise
+# region by a spatial transition zone between r_lo and r_hi, averages the
+# result over time, snaps values within dlambda_min of 0 or 1, and fixes the
+# detection value in two zones (a precise hemisphere under the tip, fast
+# surface atoms outside it).  The formulas themselves belong to the cited
+# adaptive-precision method, which is not part of the paper; the readings
+# taken here (all in the ACE-weight convention mu = 1 - lambda_paper):
+#
+#   CSP_i   = sum of the n/2 smallest |d_a + d_b|^2 over the pairs a < b of
+#             the n nearest neighbours (n = 14; ranked by the canonical r^2,
+#             ties by index); r^2 and the pair sums in FP64 with every
+#             operation rounded separately, the n/2 values summed in
+#             ascending order;
+#   average c_i <- c_i + (CSP_i - c_i) / N_csp (the first update sets c_i);
+#   mu0_i   = 0 for c_i <= CSP_lo, 1 for c_i >= CSP_hi, between
+#             (1 - cos(pi (c_i - CSP_lo)/(CSP_hi - CSP_lo)))/2;
+#             mu0_i = 1 inside the precise ball (|r_i - centre| <= r_precise),
+#             else mu0_i = 0 for surface atoms (z_i >= z_surface_min);
+#   mu_i    = max over j (including i) with r_ij < r_hi of mu0_j g(r_ij),
+#             g = 1 for r <= r_lo, (1 + cos(pi (r - r_lo)/(r_hi - r_lo)))/2
+#             below r_hi (minimum-image distances);
+#   average m_i <- m_i + (mu_i - m_i) / N_lambda (the first update sets m_i);
+#   lambda_i = 0 if m_i < dlambda_min, 1 if m_i > 1 - dlambda_min, else m_i.
+#
+# Parity unpinned: the time averaging, the ramp and transition shapes and
+# the snapping are readings of the absent method paper; the pins below fix
+# the CSP definition, the closed forms of each step and their composition.
+
+from dataclasses import dataclass
+
+from .geometry import displacement, r2_of
+
+
+@dataclass
+class SwitchParams:
+    csp_lo: float = 1.5
+    csp_hi: float = 1.6
+    n_csp: int = 14
+    n_csp_avg: int = 110
+    r_lo: float = 4.0
+    r_hi: float = 12.0
+    n_lambda_avg: int = 110
+    dlambda_min: float = 0.01
+    centre: tuple = (0.0, 0.0, 0.0)
+    r_precise: float = -1.0
+    z_surface_min: float = float("inf")
+
+
+def csp_of(d, n_nb=14):
+    """CSP of one atom from its bond vectors d[j, 3] in neighbour-index order
+    (ties in r^2 keep that order)."""
+    d = np.asarray(d, dtype=np.float64)
+    if len(d) < n_nb:
+        raise ValueError("fewer neighbours than the CSP needs")
+    r2 = r2_of(d)
+    near = d[np.argsort(r2, kind="stable")[:n_nb]]
+    sums = []
+    for a in range(n_nb):
+        for b in range(a + 1, n_nb):
+            s = near[a] + near[b]
+            sums.append((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2])
+    total = 0.0
+    for v in sorted(sums)[: n_nb // 2]:
+        total += v
+    return total
+
+
+def csp_all(S, rows, n_nb=14):
+    """CSP of every atom; rows[i] = (j ascending, d) neighbour lists."""
+    return np.array([csp_of(rows[i][1], n_nb) for i in range(S.n_atoms)])
+
+
+def ramp(c, lo, hi):
+    c = np.asarray(c, dtype=np.float64)
+    t = np.clip((c - lo) / (hi - lo), 0.0, 1.0)
+    return np.where(c <= lo, 0.0, np.where(c >= hi, 1.0, 0.5 * (1.0 - np.cos(math.pi * t))))
+
+
+def transition(r, r_lo, r_hi):
+    r = np.asarray(r, dtype=np.float64)
+    band = 0.5 * (1.0 + np.cos(math.pi * (r - r_lo) / (r_hi - r_lo)))
+    return np.where(r <= r_lo, 1.0, np.where(r < r_hi, band, 0.0))
+
+
+def detection(pos, c_avg, p: SwitchParams):
+    mu0 = ramp(c_avg, p.csp_lo, p.csp_hi)
+    if p.r_precise > 0:
+        inside = np.sqrt(np.sum((pos - np.asarray(p.centre)[None, :]) ** 2, 1)) <= p.r_precise
+    else:
+        inside = np.zeros(len(pos), bool)
+    surf = (pos[:, 2] >= p.z_surface_min) & ~inside
+    return np.where(inside, 1.0, np.where(surf, 0.0, mu0))
+
+
+def spread(S, mu0, p: SwitchParams):
+    """mu_i = max_j mu0_j g(r_ij) over sources j with mu0_j > 0 (brute force
+    over every atom of the source's system, minimum image)."""
+    mu = np.zeros(S.n_atoms)
+    for j in np.nonzero(mu0 > 0)[0]:
+        s = S.sys_of[j]
+        lo, hi = S.sys_offset[s], S.sys_offset[s + 1]
+        d = displacement(S.pos[j][None, :], S.pos[lo:hi], S.box[s], S.periodic, S.Hi[s])
+        r = np.sqrt(r2_of(d))
+        mu[lo:hi] = np.maximum(mu[lo:hi], mu0[j] * transition(r, p.r_lo, p.r_hi))
+    return mu
+
+
+def snap(m, dmin):
+    m = np.asarray(m, dtype=np.float64)
+    return np.where(m < dmin, 0.0, np.where(m > 1.0 - dmin, 1.0, m))
+
+
+class DynamicSwitching:
+    """State (time averages) and one update per call, in the order above."""
+
+    def __init__(self, params: SwitchParams):
+        self.p = params
+        self.c_avg = None
+        self.m_avg = None
+
+    def update(self, S, rows=None):
+        p = self.p
+        rows = S.neighbour_lists() if rows is None else rows
+        c = csp_all(S, rows, p.n_csp)
+        self.c_avg = c.copy() if self.c_avg is None else self.c_avg + (c - self.c_avg) / p.n_csp_avg
+        mu0 = detection(S.pos, self.c_avg, p)
+        mu = spread(S, mu0, p)
+        self.m_avg = mu.copy() if self.m_avg is None else self.m_avg + (mu - self.m_avg) / p.n_lambda_avg
+        return snap(self.m_avg, p.dlambda_min)
