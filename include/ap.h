@@ -177,6 +177,43 @@ typedef struct {
   const uint8_t* mask; /* device, n_atoms, kind 3 only */
 } ap_lambda_rule;
 
+/* Dynamic switching (section "Adaptive-precision potential": the switching
+ * parameter follows the centro-symmetry parameter (CSP) during the run, with
+ * fixed zones; appendix "Switching function" and the table of the
+ * adaptive-precision model's parameters).  One update, in this order, with
+ * mu = the ACE weight (1 - the paper's lambda):
+ *   CSP_i = sum of the n_csp/2 smallest |d_a + d_b|^2 over the pairs of the
+ *     n_csp nearest neighbours (ranked by the canonical r^2, ties by index),
+ *     summed in ascending order; (n_csp/2) (2 cutoff)^2 for atoms with fewer
+ *     than n_csp neighbours;
+ *   csp_avg_i <- csp_avg_i + (CSP_i - csp_avg_i) / n_csp_avg;
+ *   mu0_i = 0 for csp_avg_i <= csp_lo, 1 for >= csp_hi, between
+ *     (1 - cos(pi (csp_avg_i - csp_lo)/(csp_hi - csp_lo)))/2; then 1 inside
+ *     the precise ball (|r_i - centre|^2 <= r_precise^2), else 0 for atoms
+ *     with z_i >= z_surface_min (fast surface);
+ *   mu_i = max over j with r_ij^2 < r_hi^2 of mu0_j g(r_ij), g = 1 for
+ *     r <= r_lo, (1 + cos(pi (r - r_lo)/(r_hi - r_lo)))/2 below r_hi;
+ *   lambda_avg_i <- lambda_avg_i + (mu_i - lambda_avg_i) / n_lambda_avg;
+ *   lambda_i = lambda_avg_i, set to 0 below dlambda_min and to 1 above
+ *     1 - dlambda_min.
+ * The first update (initialised == 0) sets both averages to the current
+ * values.  The paper's values for W: n_csp 14, csp_lo 1.5, csp_hi 1.6 A^2,
+ * n_csp_avg = n_lambda_avg = 110, r_lo 4, r_hi 12 A, dlambda_min 0.01. */
+typedef struct {
+  double csp_lo, csp_hi;   /* A^2, csp_lo < csp_hi */
+  int32_t n_csp;           /* neighbours in the CSP: even, 2..16 */
+  int32_t n_csp_avg;       /* length of the CSP time average (updates), >= 1 */
+  double r_lo, r_hi;       /* spatial transition zone (A), 0 <= r_lo < r_hi */
+  int32_t n_lambda_avg;    /* length of the time average of mu, >= 1 */
+  double dlambda_min;      /* snapping width, in [0, 0.5) */
+  double centre[3];        /* centre of the precise ball (first-contact point) */
+  double r_precise;        /* its radius; <= 0: no precise ball */
+  double z_surface_min;    /* surface zone outside the ball: z >= this */
+  double* csp_avg;         /* device [n_atoms]: state, caller-owned */
+  double* lambda_avg;      /* device [n_atoms]: state, caller-owned */
+  int32_t initialised;     /* [host] 0 before the first update; set to 1 by it */
+} ap_switching;
+
 /* Create a context on HIP device `device`.  eam and/or ace may be NULL (the
  * matching force call then returns AP_ERR_ARG).  The model is copied and
  * folded into device tables; host arrays may be freed afterwards. */
@@ -200,6 +237,18 @@ ap_status ap_build_neighbors(ap_ctx* ctx, const ap_systems* sys, const double* p
 ap_status ap_blend(ap_ctx* ctx, const ap_systems* sys, const double* pos,
                    const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                    int32_t* n_ace, void* stream);
+
+/* One update of the dynamic switching rule (ap_switching): lambda[n_atoms]
+ * (ACE weight) and the ascending list ace_list[0 .. *n_ace) of atoms with
+ * lambda > 0.  nl must be the list ap_build_neighbors built on this context
+ * at these positions (its cell list is reused for the transition zone).
+ * Orthorhombic systems only (else AP_ERR_UNSUPPORTED); r_hi and every
+ * periodic width must satisfy 2 r_hi <= width (else AP_ERR_BOX).
+ * Deterministic: every decision is taken on FP64 values in a fixed order and
+ * the transition zone is a maximum. */
+ap_status ap_switching_update(ap_ctx* ctx, const ap_systems* sys, const double* pos,
+                              const ap_nlist* nl, ap_switching* sw, double* lambda,
+                              int32_t* ace_list, int32_t* n_ace, void* stream);
 
 /* ap_blend for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
@@ -269,6 +318,8 @@ typedef struct {
   double* e_ind;          /* device scalar or NULL */
   double* load;           /* device scalar or NULL */
   int32_t check_every;    /* > 0: synchronise and check overflow / finiteness every k steps */
+  ap_switching* switching;/* [host] non-NULL: lambda from ap_switching_update every evaluation
+                             (after the neighbour build) instead of `rule` */
 } ap_md_state;
 
 /* n_steps == 0: one force evaluation at the current positions

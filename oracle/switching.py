@@ -65,15 +65,18 @@ def ace_list(lam):
 #             the n nearest neighbours (n = 14; ranked by the canonical r^2,
 #             ties by index); r^2 and the pair sums in FP64 with every
 #             operation rounded separately, the n/2 values summed in
-#             ascending order;
+#             ascending order; an atom with fewer than n neighbours within
+#             the cutoff r_c gets the largest value a full set could have,
+#             (n/2) (2 r_c)^2 (always detected, finite for the averages);
 #   average c_i <- c_i + (CSP_i - c_i) / N_csp (the first update sets c_i);
 #   mu0_i   = 0 for c_i <= CSP_lo, 1 for c_i >= CSP_hi, between
 #             (1 - cos(pi (c_i - CSP_lo)/(CSP_hi - CSP_lo)))/2;
-#             mu0_i = 1 inside the precise ball (|r_i - centre| <= r_precise),
+#             mu0_i = 1 inside the precise ball (|r_i - centre|^2 <=
+#             r_precise^2, the squared distance summed as (x^2 + y^2) + z^2),
 #             else mu0_i = 0 for surface atoms (z_i >= z_surface_min);
-#   mu_i    = max over j (including i) with r_ij < r_hi of mu0_j g(r_ij),
+#   mu_i    = max over j (including i) with r_ij^2 < r_hi^2 of mu0_j g(r_ij),
 #             g = 1 for r <= r_lo, (1 + cos(pi (r - r_lo)/(r_hi - r_lo)))/2
-#             below r_hi (minimum-image distances);
+#             below r_hi (canonical minimum-image displacement r_i - r_j);
 #   average m_i <- m_i + (mu_i - m_i) / N_lambda (the first update sets m_i);
 #   lambda_i = 0 if m_i < dlambda_min, 1 if m_i > 1 - dlambda_min, else m_i.
 #
@@ -101,12 +104,12 @@ class SwitchParams:
     z_surface_min: float = float("inf")
 
 
-def csp_of(d, n_nb=14):
+def csp_of(d, n_nb=14, rc=5.5):
     """CSP of one atom from its bond vectors d[j, 3] in neighbour-index order
-    (ties in r^2 keep that order)."""
-    d = np.asarray(d, dtype=np.float64)
+    (ties in r^2 keep that order); rc: the neighbour-list cutoff."""
+    d = np.asarray(d, dtype=np.float64).reshape(-1, 3)
     if len(d) < n_nb:
-        raise ValueError("fewer neighbours than the CSP needs")
+        return (n_nb // 2) * (2.0 * rc) * (2.0 * rc)
     r2 = r2_of(d)
     near = d[np.argsort(r2, kind="stable")[:n_nb]]
     sums = []
@@ -122,7 +125,7 @@ def csp_of(d, n_nb=14):
 
 def csp_all(S, rows, n_nb=14):
     """CSP of every atom; rows[i] = (j ascending, d) neighbour lists."""
-    return np.array([csp_of(rows[i][1], n_nb) for i in range(S.n_atoms)])
+    return np.array([csp_of(rows[i][1], n_nb, S.cutoff) for i in range(S.n_atoms)])
 
 
 def ramp(c, lo, hi):
@@ -140,7 +143,7 @@ def transition(r, r_lo, r_hi):
 def detection(pos, c_avg, p: SwitchParams):
     mu0 = ramp(c_avg, p.csp_lo, p.csp_hi)
     if p.r_precise > 0:
-        inside = np.sqrt(np.sum((pos - np.asarray(p.centre)[None, :]) ** 2, 1)) <= p.r_precise
+        inside = r2_of(pos - np.asarray(p.centre)[None, :]) <= p.r_precise * p.r_precise
     else:
         inside = np.zeros(len(pos), bool)
     surf = (pos[:, 2] >= p.z_surface_min) & ~inside
@@ -155,8 +158,9 @@ def spread(S, mu0, p: SwitchParams):
         s = S.sys_of[j]
         lo, hi = S.sys_offset[s], S.sys_offset[s + 1]
         d = displacement(S.pos[j][None, :], S.pos[lo:hi], S.box[s], S.periodic, S.Hi[s])
-        r = np.sqrt(r2_of(d))
-        mu[lo:hi] = np.maximum(mu[lo:hi], mu0[j] * transition(r, p.r_lo, p.r_hi))
+        r2 = r2_of(d)
+        g = np.where(r2 < p.r_hi * p.r_hi, transition(np.sqrt(r2), p.r_lo, p.r_hi), 0.0)
+        mu[lo:hi] = np.maximum(mu[lo:hi], mu0[j] * g)
     return mu
 
 

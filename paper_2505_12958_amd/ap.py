@@ -65,6 +65,14 @@ class LambdaRule(C.Structure):
                 ("mask", C.c_void_p)]
 
 
+class Switching(C.Structure):
+    _fields_ = [("csp_lo", C.c_double), ("csp_hi", C.c_double), ("n_csp", C.c_int32),
+                ("n_csp_avg", C.c_int32), ("r_lo", C.c_double), ("r_hi", C.c_double),
+                ("n_lambda_avg", C.c_int32), ("dlambda_min", C.c_double),
+                ("centre", C.c_double * 3), ("r_precise", C.c_double), ("z_surface_min", C.c_double),
+                ("csp_avg", C.c_void_p), ("lambda_avg", C.c_void_p), ("initialised", C.c_int32)]
+
+
 class MDState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("force", C.c_void_p),
                 ("e_atom", C.c_void_p), ("lambda_", C.c_void_p), ("mass", C.c_void_p),
@@ -73,7 +81,8 @@ class MDState(C.Structure):
                 ("ind_centre", C.c_double * 3), ("ind_vel", C.c_double * 3),
                 ("ind_dir", C.c_double * 3), ("ind_R", C.c_double), ("ind_K", C.c_double),
                 ("virial", C.c_void_p), ("e_sys", C.c_void_p), ("e_ind", C.c_void_p),
-                ("load", C.c_void_p), ("check_every", C.c_int32)]
+                ("load", C.c_void_p), ("check_every", C.c_int32),
+                ("switching", C.POINTER(Switching))]
 
 
 _lib = None
@@ -105,19 +114,21 @@ def lib():
                                   vp, vp, vp, vp]
         L.ap_reduce_energy.argtypes = [vp, C.POINTER(Systems), vp, vp, vp]
         L.ap_step.argtypes = [vp, C.POINTER(Systems), C.POINTER(MDState), i32, vp]
+        L.ap_switching_update.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList),
+                                          C.POINTER(Switching), vp, vp, vp, vp]
         L.ap_check.argtypes = [vp, vp]
         L.ap_profile.argtypes = [vp, i32]
         L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
         L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
         for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_blend_noalloc",
-                  "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
+                  "ap_switching_update", "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
 
 
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
-           "ap_blend_noalloc",
+           "ap_blend_noalloc", "ap_switching_update",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
            "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
 PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce",
@@ -267,6 +278,13 @@ class Context:
                             _ptr(ace_list), _ptr(n_ace), _stream())
         self._check(st)
 
+    def switching_update(self, sysarg, pos, nl, sw, lam, ace_list, n_ace):
+        """One update of the dynamic switching rule (sw: DynamicSwitching)."""
+        st = lib().ap_switching_update(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(nl.struct()),
+                                       C.byref(sw.c), _ptr(lam), _ptr(ace_list), _ptr(n_ace),
+                                       _stream())
+        self._check(st)
+
     def blend_noalloc(self, sysarg, pos, rule, lam, ace_list, n_ace, mask=None):
         r = rule_struct(rule, mask)
         st = lib().ap_blend_noalloc(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
@@ -365,14 +383,45 @@ class MD:
         c.virial, c.e_sys = self.virial.data_ptr(), self.e_sys.data_ptr()
         c.e_ind, c.load = self.e_ind.data_ptr(), self.load.data_ptr()
         c.check_every = 0
+        c.switching = None
         self.c = c
+        self.switching = None
         self.ind_centre = np.array(c.ind_centre[:])
+
+    def use_switching(self, sw):
+        """Take lambda from the dynamic switching rule sw (DynamicSwitching)
+        in every force evaluation of ap_step."""
+        self.switching = sw
+        self.c.switching = C.pointer(sw.c)
 
     def pull_indenter(self):
         self.ind_centre = np.array(self.c.ind_centre[:])
 
 
 AP_LAMBDA_GIVEN = 4
+
+
+class DynamicSwitching:
+    """ap_switching with its device state (time averages) kept alive.
+
+    The paper's values for W (table of the adaptive-precision model's
+    parameters) are the defaults; `centre`/`r_precise` give the precise ball
+    and `z_surface_min` the fast surface zone."""
+
+    def __init__(self, n_atoms, *, csp_lo=1.5, csp_hi=1.6, n_csp=14, n_csp_avg=110, r_lo=4.0,
+                 r_hi=12.0, n_lambda_avg=110, dlambda_min=0.01, centre=(0.0, 0.0, 0.0),
+                 r_precise=-1.0, z_surface_min=float("inf"), device="cuda"):
+        self.csp_avg = torch.zeros(max(1, n_atoms), dtype=torch.float64, device=device)
+        self.lambda_avg = torch.zeros(max(1, n_atoms), dtype=torch.float64, device=device)
+        c = Switching()
+        c.csp_lo, c.csp_hi, c.n_csp, c.n_csp_avg = csp_lo, csp_hi, n_csp, n_csp_avg
+        c.r_lo, c.r_hi, c.n_lambda_avg, c.dlambda_min = r_lo, r_hi, n_lambda_avg, dlambda_min
+        for k in range(3):
+            c.centre[k] = float(centre[k])
+        c.r_precise, c.z_surface_min = float(r_precise), float(z_surface_min)
+        c.csp_avg, c.lambda_avg = self.csp_avg.data_ptr(), self.lambda_avg.data_ptr()
+        c.initialised = 0
+        self.c = c
 
 
 def given_rule():

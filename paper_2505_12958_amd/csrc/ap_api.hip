@@ -988,7 +988,8 @@ ap_status ap_destroy(ap_ctx* c) {
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
                     &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
-                    &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn})
+                    &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn, &ctx->sw_csp, &ctx->sw_mu0,
+                    &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc})
     release(*b);
   delete ctx;
   return AP_OK;
@@ -1035,6 +1036,7 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
                                (const double4*)ctx->cell_pos.p, nl->nbr, nl->count, nl->capacity,
                                flags, (int32_t*)ctx->cell_big.p, s));
   if (nl->rev) AP_HIP(launch_rev((int32_t)N, nl->nbr, nl->count, nl->rev, s));
+  ctx->cells_n_atoms = N;
   if (needed_capacity) {
     int32_t need = 0;
     AP_HIP(hipMemcpyAsync(&need, flags, 4, hipMemcpyDeviceToHost, s));
@@ -1290,6 +1292,51 @@ ap_status ap_indenter(ap_ctx* c, const ap_systems* sys, const double* pos, const
   return AP_OK;
 }
 
+ap_status ap_switching_update(ap_ctx* c, const ap_systems* sys, const double* pos,
+                              const ap_nlist* nl, ap_switching* sw, double* lambda,
+                              int32_t* ace_list, int32_t* n_ace, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if (!sw || !lambda || !ace_list || !n_ace) return fail(ctx, AP_ERR_ARG, "switching arguments missing");
+  if (!(sw->csp_lo < sw->csp_hi) || sw->n_csp < 2 || sw->n_csp > 16 || (sw->n_csp & 1) ||
+      sw->n_csp_avg < 1 || sw->n_lambda_avg < 1 || !(sw->r_lo >= 0.0) || !(sw->r_lo < sw->r_hi) ||
+      !(sw->dlambda_min >= 0.0 && sw->dlambda_min < 0.5) || !std::isfinite(sw->r_hi))
+    return fail(ctx, AP_ERR_ARG, "switching parameters out of range");
+  if ((st = check_nl(ctx, nl))) return st;
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  const int64_t N = sv.n_atoms;
+  if (N > 0 && (!pos || !sw->csp_avg || !sw->lambda_avg)) return fail(ctx, AP_ERR_ARG, "pos or switching state is NULL");
+  if (!ctx->sys.all_ortho) return fail(ctx, AP_ERR_UNSUPPORTED, "dynamic switching needs orthorhombic systems");
+  for (int k = 0; k < 3; ++k)
+    if (sys->periodic[k])
+      for (int q = 0; q < sys->n_systems; ++q)
+        if (sys->box[9 * q + 4 * k] < 2.0 * sw->r_hi)
+          return fail(ctx, AP_ERR_BOX, "a periodic width is below twice the transition range r_hi");
+  if (ctx->cells_n_atoms != N) return fail(ctx, AP_ERR_ARG, "build the neighbour list on this context first");
+  if ((st = ensure(ctx, ctx->sw_csp, 8 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->sw_mu0, 8 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->sw_mu, 8 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->sw_flag, 4 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->sw_src, 4 * (size_t)std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->sw_nsrc, 256)) ||
+      (st = ensure(ctx, ctx->scan_tmp, 4 * ((size_t)std::max<int64_t>(ctx->sys.n_cells, N) / 4096 + 2))))
+    return st;
+  const double full = (sw->n_csp / 2) * (2.0 * sys->cutoff) * (2.0 * sys->cutoff);
+  PhaseTimer timer(ctx, AP_PHASE_BLEND, s);
+  AP_HIP(launch_switching(sv, pos, nl->nbr, nl->count, nl->capacity, (const int32_t*)ctx->cell_of.p,
+                          (const int32_t*)ctx->cell_start.p, (const int32_t*)ctx->cell_count.p,
+                          (const int32_t*)ctx->cell_atoms.p, (const double4*)ctx->cell_pos.p, *sw, full,
+                          (double*)ctx->sw_csp.p, (double*)ctx->sw_mu0.p,
+                          (unsigned long long*)ctx->sw_mu.p, (int32_t*)ctx->sw_flag.p,
+                          (int32_t*)ctx->sw_src.p, (int32_t*)ctx->sw_nsrc.p, (int32_t*)ctx->scan_tmp.p,
+                          lambda, ace_list, n_ace, s));
+  sw->initialised = 1;
+  return AP_OK;
+}
+
 ap_status ap_blend_noalloc(ap_ctx* c, const ap_systems* sys, const double* pos,
                            const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                            int32_t* n_ace, void* stream) {
@@ -1360,9 +1407,17 @@ ap_status ap_check(ap_ctx* c, void* stream) {
 static ap_status force_eval(Ctx* ctx, const ap_systems* sys, ap_md_state* st, hipStream_t s) {
   ap_status r;
   const int64_t N = sys->n_atoms;
-  if ((r = ap_blend((ap_ctx*)ctx, sys, st->pos, &st->rule, st->lambda, st->ace_list, st->n_ace, s)))
-    return r;
-  if ((r = ap_build_neighbors((ap_ctx*)ctx, sys, st->pos, &st->nl, nullptr, s))) return r;
+  if (st->switching) {
+    // the dynamic rule needs the neighbour list (and its cells) of these positions
+    if ((r = ap_build_neighbors((ap_ctx*)ctx, sys, st->pos, &st->nl, nullptr, s))) return r;
+    if ((r = ap_switching_update((ap_ctx*)ctx, sys, st->pos, &st->nl, st->switching, st->lambda,
+                                 st->ace_list, st->n_ace, s)))
+      return r;
+  } else {
+    if ((r = ap_blend((ap_ctx*)ctx, sys, st->pos, &st->rule, st->lambda, st->ace_list, st->n_ace, s)))
+      return r;
+    if ((r = ap_build_neighbors((ap_ctx*)ctx, sys, st->pos, &st->nl, nullptr, s))) return r;
+  }
   bool written = false;
   if (ctx->has_eam) {
     if ((r = ap_eam_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->e_atom, st->force,

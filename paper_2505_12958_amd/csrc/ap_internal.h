@@ -177,6 +177,8 @@ struct Ctx {
   Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
+  Buffer sw_csp, sw_mu0, sw_mu, sw_flag, sw_src, sw_nsrc;   // dynamic switching scratch
+  int64_t cells_n_atoms = -1;           // atoms of the last neighbour build (its cell list)
   void* static_scratch = nullptr;      // this device's address of the static scratch array
   // launch mode of the mixed rank phase: forced (AP_RANK_MODE, >= 0) or tuned
   // per bucket of the atom count (timed on first use, optionally cached in
@@ -264,6 +266,15 @@ hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* 
                              const double* force, const double* mass, const uint8_t* fixed,
                              double dt, bool drift, hipStream_t s);
 hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s);
+// dynamic switching (k_switch.hip)
+hipError_t launch_switching(const SysView& sv, const double* pos, const int32_t* nbr,
+                            const int32_t* count, int32_t cap, const int32_t* cell_of,
+                            const int32_t* cell_start, const int32_t* cell_count,
+                            const int32_t* cell_atoms, const double4* cell_pos,
+                            const ap_switching& sw, double csp_full, double* csp, double* mu0,
+                            unsigned long long* mu_bits, int32_t* flag, int32_t* src, int32_t* n_src,
+                            int32_t* scan_tmp, double* lambda, int32_t* ace_list, int32_t* n_ace,
+                            hipStream_t s);
 // EAM (k_eam.hip)
 hipError_t launch_pack_pos(int32_t n, const double* pos, double4* p4, hipStream_t s);
 hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,

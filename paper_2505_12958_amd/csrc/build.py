@@ -12,7 +12,7 @@ OUT = os.path.join(PKG, "libap.so")
 OBJ = os.path.join(PKG, "_build")
 
 SOURCES = ["ap_api.hip", "k_nbr.hip", "k_misc.hip", "k_eam.hip", "k_ace.hip", "k_ace_mixed.hip",
-           "k_ace_rank_fused.hip"]
+           "k_ace_rank_fused.hip", "k_switch.hip"]
 # (source, object name, extra flags): the mixed rank kernels are compiled once
 # per coupled rank L, in parallel
 UNITS = [(s, s.replace(".hip", ""), []) for s in SOURCES] + [
@@ -28,6 +28,8 @@ EXTRA = {
     # the neighbour test must be bit-exact: no fused multiply-add anywhere in it
     "k_nbr.hip": ["-ffp-contract=off"],
     "ap_api.hip": ["-ffp-contract=off"],
+    # the CSP and the zone decisions are bit-exact against the oracle too
+    "k_switch.hip": ["-ffp-contract=off"],
 }
 
 

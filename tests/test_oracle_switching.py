@@ -55,6 +55,8 @@ def test_csp_invariances():
     # only the 14 nearest count: adding far neighbours changes nothing
     far = np.vstack([d, d[:3] * 1.8])
     assert csp_of(far) == c
+    # fewer than 14 neighbours: the largest value a full set could have
+    assert csp_of(d[:13]) == 7 * 11.0 * 11.0
 
 
 def test_ramp_and_transition_closed_forms():
