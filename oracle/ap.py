@@ -69,8 +69,16 @@ class APOracle:
                     G[k] = G[k] + lam[atoms[k]] * g[t]
         return e_eam, e_ace, G, rho, phi
 
-    def evaluate(self, sysm: Systems, lam, nl=None, indenter_args=None, mobile=None):
-        """Full evaluation: per-atom energies, forces, per-system energy and virial."""
+    def evaluate(self, sysm: Systems, lam, nl=None, indenter_args=None, mobile=None,
+                 lambda_rule=None):
+        """Full evaluation: per-atom energies, forces, per-system energy and virial.
+
+        lambda_rule (a geometric switching rule): lambda is the rule's value
+        at these positions and the forces are the full -dE/dr with
+        lambda = lambda(r): the fixed-lambda forces plus
+        -(E_i^ACE - E_i^EAM) d lambda_i / d r_i on each atom of the taper
+        band, whose virial is -(r_i - centre) (x) (E_i^ACE - E_i^EAM)
+        d lambda_i / d r_i."""
         N = sysm.n_atoms
         lam = np.asarray(lam, dtype=np.float64)
         if nl is None:
@@ -90,6 +98,16 @@ class APOracle:
             F[i] += g.sum(0)
             np.subtract.at(F, js, g)
             Wv[sysm.sys_of[i]] -= d.T @ g
+        if lambda_rule is not None:
+            from .switching import lambda_and_gradient
+            lam_r, grad = lambda_and_gradient(sysm.pos, lambda_rule)
+            if np.any(lam_r != lam):
+                raise ValueError("lambda_rule does not give the lambda passed in")
+            G = (e_ace - e_eam)[:, None] * grad
+            F -= G
+            dvec = sysm.pos - np.asarray(lambda_rule.centre)[None, :]
+            for i in np.nonzero(np.any(G != 0.0, axis=1))[0]:
+                Wv[sysm.sys_of[i]] -= np.outer(dvec[i], G[i])
         e_sys = np.array([e_atom[sysm.sys_offset[s]:sysm.sys_offset[s + 1]].sum() for s in range(ns)])
         out = dict(e_atom=e_atom, e_eam=e_eam, e_ace=e_ace, forces=F, virial=Wv, e_sys=e_sys,
                    rho=rho, phi=phi, nl=nl, lam=lam)

@@ -43,6 +43,27 @@ def lambda_of(pos, rule):
     return np.where(surf, 0.0, lam)
 
 
+def lambda_and_gradient(pos, rule):
+    """lambda_i and d lambda_i / d r_i of a geometric rule (sphere,
+    hemisphere, mask): nonzero only in the cosine band r_full < d < r_full +
+    taper, and zero where the mask or the surface override fixes lambda.
+    Constant and given rules have no gradient."""
+    pos = np.asarray(pos, dtype=np.float64)
+    lam = lambda_of(pos, rule)
+    grad = np.zeros_like(pos)
+    if rule.kind in (1, 2, 3):
+        dvec = pos - np.asarray(rule.centre)[None, :]
+        d = np.sqrt(np.sum(dvec * dvec, axis=1))
+        band = (d > rule.r_full) & (d < rule.r_full + rule.taper)
+        fixed = np.zeros(len(pos), bool)
+        if rule.kind == 3 and rule.mask is not None:
+            fixed |= np.asarray(rule.mask) != 0
+        band &= ~fixed
+        dl = -0.5 * math.pi / rule.taper * np.sin(math.pi * (d - rule.r_full) / rule.taper)
+        grad[band] = (dl[band] / d[band])[:, None] * dvec[band]
+    return lam, grad
+
+
 def ace_list(lam):
     """Indices with lambda > 0, ascending."""
     return np.nonzero(np.asarray(lam) > 0.0)[0]

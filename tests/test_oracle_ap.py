@@ -168,3 +168,65 @@ def test_forces_at_equals_full_evaluation(model, cell):
     # with the k-d-tree finder of the full-size tests as well
     F2, _, _ = orc.forces_at(S, lam, atoms[:6], S.neighbour_finder())
     assert np.abs(F2 - out["forces"][atoms[:6]]).max() <= 1e-12 * np.abs(out["forces"]).max()
+
+
+def sphere_rule(box, r_full=2.0, taper=3.5):
+    from paper_2505_12958_amd.workloads import LambdaRule
+    L = box[0][0][0]
+    return LambdaRule(1, centre=np.array([L / 2, L / 2, L / 2]), r_full=r_full, taper=taper,
+                      z_surface_min=1e9)
+
+
+def test_forces_with_position_dependent_lambda_match_fd(model):
+    """lambda = lambda(r) by the cosine-tapered sphere rule (section
+    "Adaptive-precision potential", the AP energy with its switching
+    parameter): the forces with the -(E^ACE - E^EAM) grad lambda term are
+    -dE/dr of the energy whose lambda follows the positions."""
+    from oracle.switching import lambda_and_gradient, lambda_of
+    pos, box = jittered_bcc(4, 3.165, 0.08, 9)
+    rule = sphere_rule(box)
+    orc = APOracle(*model)
+    S = Systems(pos, box, [0, len(pos)], (True, True, True), 5.5)
+    lam = lambda_of(pos, rule)
+    _, grad = lambda_and_gradient(pos, rule)
+    band = np.nonzero(np.any(grad != 0, axis=1))[0]
+    assert len(band) >= 20
+    out = orc.evaluate(S, lam, lambda_rule=rule)
+
+    def energy(p):
+        Sp = Systems(p, box, [0, len(p)], (True, True, True), 5.5)
+        return float(np.sum(orc.evaluate(Sp, lambda_of(p, rule))["e_atom"]))
+
+    atoms = [int(band[0]), int(band[len(band) // 2]), int(band[-1]), 3]
+    fd = fd_forces(energy, pos, atoms, h=2e-4)
+    ref = out["forces"][atoms]
+    assert np.abs(fd - ref).max() < 1e-7 * np.abs(ref).max()
+    # the term matters: the fixed-lambda forces differ from the FD
+    fixed = orc.evaluate(S, lam)["forces"][atoms]
+    assert np.abs(fd - fixed).max() > 1e-4 * np.abs(ref).max()
+
+
+def test_virial_with_position_dependent_lambda_is_minus_strain_derivative(model):
+    from oracle.switching import lambda_of
+    pos, box = jittered_bcc(4, 3.165, 0.08, 9)
+    rule = sphere_rule(box)
+    orc = APOracle(*model)
+    S = Systems(pos, box, [0, len(pos)], (True, True, True), 5.5)
+    W = orc.evaluate(S, lambda_of(pos, rule), lambda_rule=rule)["virial"][0]
+
+    def energy(eps):
+        F = np.eye(3) + eps
+        p = pos @ F.T
+        b = box @ F.T
+        r = sphere_rule(box)
+        r.centre = r.centre @ F.T
+        Sp = Systems(p, b, [0, len(p)], (True, True, True), 5.5)
+        return float(np.sum(orc.evaluate(Sp, lambda_of(p, r))["e_atom"]))
+
+    h = 1e-5
+    dE = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3)); e[a, b] = h
+            dE[a, b] = (energy(e) - energy(-e)) / (2 * h)
+    assert np.abs(W + dE.T).max() < 1e-6 * np.abs(W).max()
