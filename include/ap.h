@@ -238,6 +238,21 @@ ap_status ap_blend(ap_ctx* ctx, const ap_systems* sys, const double* pos,
                    const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                    int32_t* n_ace, void* stream);
 
+/* Forces of a switching parameter that follows the positions (section
+ * "Adaptive-precision potential": E = sum_i [lambda_i E_i^ACE + (1 - lambda_i)
+ * E_i^EAM] with lambda_i = lambda(r_i) of a geometric rule).  For the rule
+ * kinds 1-3 it adds -(E_i^ACE - E_i^EAM) d lambda_i / d r_i to force[3][n]
+ * on every atom of the cosine band (0 < lambda_i < 1; masked and surface
+ * atoms have lambda 0 or 1 and no gradient), using the unweighted per-atom
+ * energies of the last ap_eam_forces and ap_ace_forces calls on this context
+ * (same positions and lambda); virial (NULL: skipped) gets
+ * -sum_i (r_i - centre) (x) (E_i^ACE - E_i^EAM) d lambda_i / d r_i added.
+ * With it the forces are the full -dE/dr of that energy.  Other rule kinds
+ * add nothing. */
+ap_status ap_lambda_gradient(ap_ctx* ctx, const ap_systems* sys, const double* pos,
+                             const ap_lambda_rule* rule, const double* lambda, double* force,
+                             double* virial, void* stream);
+
 /* One update of the dynamic switching rule (ap_switching): lambda[n_atoms]
  * (ACE weight) and the ascending list ace_list[0 .. *n_ace) of atoms with
  * lambda > 0.  nl must be the list ap_build_neighbors built on this context
@@ -320,6 +335,8 @@ typedef struct {
   int32_t check_every;    /* > 0: synchronise and check overflow / finiteness every k steps */
   ap_switching* switching;/* [host] non-NULL: lambda from ap_switching_update every evaluation
                              (after the neighbour build) instead of `rule` */
+  int32_t lambda_gradient;/* nonzero (geometric rule, EAM and ACE): forces include the
+                             term of ap_lambda_gradient */
 } ap_md_state;
 
 /* n_steps == 0: one force evaluation at the current positions

@@ -82,7 +82,7 @@ class MDState(C.Structure):
                 ("ind_dir", C.c_double * 3), ("ind_R", C.c_double), ("ind_K", C.c_double),
                 ("virial", C.c_void_p), ("e_sys", C.c_void_p), ("e_ind", C.c_void_p),
                 ("load", C.c_void_p), ("check_every", C.c_int32),
-                ("switching", C.POINTER(Switching))]
+                ("switching", C.POINTER(Switching)), ("lambda_gradient", C.c_int32)]
 
 
 _lib = None
@@ -116,19 +116,21 @@ def lib():
         L.ap_step.argtypes = [vp, C.POINTER(Systems), C.POINTER(MDState), i32, vp]
         L.ap_switching_update.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(NList),
                                           C.POINTER(Switching), vp, vp, vp, vp]
+        L.ap_lambda_gradient.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(LambdaRule), vp, vp,
+                                         vp, vp]
         L.ap_check.argtypes = [vp, vp]
         L.ap_profile.argtypes = [vp, i32]
         L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
         L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
         for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_blend_noalloc",
-                  "ap_switching_update", "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
+                  "ap_switching_update", "ap_lambda_gradient", "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
 
 
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
-           "ap_blend_noalloc", "ap_switching_update",
+           "ap_blend_noalloc", "ap_switching_update", "ap_lambda_gradient",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
            "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
 PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce",
@@ -278,6 +280,13 @@ class Context:
                             _ptr(ace_list), _ptr(n_ace), _stream())
         self._check(st)
 
+    def lambda_gradient(self, sysarg, pos, rule, lam, force, virial=None, mask=None):
+        """Add the force (and virial) of a position-dependent geometric lambda."""
+        r = rule_struct(rule, mask)
+        st = lib().ap_lambda_gradient(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
+                                      _ptr(force), _ptr(virial), _stream())
+        self._check(st)
+
     def switching_update(self, sysarg, pos, nl, sw, lam, ace_list, n_ace):
         """One update of the dynamic switching rule (sw: DynamicSwitching)."""
         st = lib().ap_switching_update(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(nl.struct()),
@@ -384,6 +393,7 @@ class MD:
         c.e_ind, c.load = self.e_ind.data_ptr(), self.load.data_ptr()
         c.check_every = 0
         c.switching = None
+        c.lambda_gradient = 0
         self.c = c
         self.switching = None
         self.ind_centre = np.array(c.ind_centre[:])

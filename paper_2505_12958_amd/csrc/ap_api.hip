@@ -989,7 +989,8 @@ ap_status ap_destroy(ap_ctx* c) {
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
                     &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn, &ctx->sw_csp, &ctx->sw_mu0,
-                    &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc})
+                    &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc,
+                    &ctx->e_eam_raw, &ctx->e_ace_raw})
     release(*b);
   delete ctx;
   return AP_OK;
@@ -1110,7 +1111,7 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   const int64_t N = sv.n_atoms;
   if (N > 0 && (!pos || !e_atom || !force)) return fail(ctx, AP_ERR_ARG, "pos/e_atom/force is NULL");
   if ((st = ensure(ctx, ctx->wfp, 8 * (size_t)N)) || (st = ensure(ctx, ctx->eF, 8 * (size_t)N)) ||
-      (st = ensure(ctx, ctx->wgt, 8 * (size_t)N)) ||
+      (st = ensure(ctx, ctx->wgt, 8 * (size_t)N)) || (st = ensure(ctx, ctx->e_eam_raw, 8 * (size_t)N)) ||
       (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
     return st;
   const bool acc = flags == AP_ACCUMULATE;
@@ -1121,7 +1122,7 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
   AP_HIP(launch_eam(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, (int32_t)N,
                     lambda, (double*)ctx->wfp.p, (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom,
-                    force, vir, acc, s));
+                    force, vir, acc, (double*)ctx->e_eam_raw.p, s));
   }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
@@ -1147,6 +1148,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if ((st = ensure(ctx, ctx->ace_row, 4 * (size_t)std::max<int64_t>(N, 1))) ||
       (st = ensure(ctx, ctx->ace_counter, 256)) ||
       (st = ensure(ctx, ctx->pair_g, gsz * 3 * (size_t)nl->capacity * std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->e_ace_raw, 8 * (size_t)std::max<int64_t>(N, 1))) ||
       (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
     return st;
   const bool acc = flags == AP_ACCUMULATE;
@@ -1161,7 +1163,8 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     PhaseTimer timer(ctx, AP_PHASE_ACE, s);
     AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
                       (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
-                      (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir, s));
+                      (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir,
+                      (double*)ctx->e_ace_raw.p, s));
   } else {
     const MixDev& mx = ctx->mix;
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
@@ -1178,7 +1181,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                               nl->capacity, (int32_t)N, lambda, ace_list, n_ace,
                               (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p, (float*)ctx->mix_A.p,
                               (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p, (float*)ctx->mix_bn.p, e_atom,
-                              vir, s, phase, mode);
+                              vir, s, phase, mode, (double*)ctx->e_ace_raw.p);
     };
     {
       PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
@@ -1337,6 +1340,36 @@ ap_status ap_switching_update(ap_ctx* c, const ap_systems* sys, const double* po
   return AP_OK;
 }
 
+ap_status ap_lambda_gradient(ap_ctx* c, const ap_systems* sys, const double* pos,
+                             const ap_lambda_rule* rule, const double* lambda, double* force,
+                             double* virial, void* stream) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ap_status st;
+  if (!rule || !lambda || !force) return fail(ctx, AP_ERR_ARG, "lambda-gradient arguments missing");
+  SysView sv;
+  if ((st = prepare_systems(ctx, sys, &sv))) return st;
+  const int64_t N = sv.n_atoms;
+  if (N > 0 && !pos) return fail(ctx, AP_ERR_ARG, "pos is NULL");
+  const bool geo = rule->kind == AP_LAMBDA_SPHERE || rule->kind == AP_LAMBDA_HEMISPHERE ||
+                   rule->kind == AP_LAMBDA_MASK;
+  if (!geo || N == 0) return AP_OK;  // lambda does not follow the positions
+  if (!(rule->taper > 0)) return fail(ctx, AP_ERR_ARG, "rule needs taper > 0");
+  if (!ctx->has_eam || !ctx->has_ace || ctx->e_eam_raw.bytes < 8 * (size_t)N ||
+      ctx->e_ace_raw.bytes < 8 * (size_t)N)
+    return fail(ctx, AP_ERR_ARG, "call ap_eam_forces and ap_ace_forces on this context first");
+  if (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))) return st;
+  double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
+  {
+    PhaseTimer timer(ctx, AP_PHASE_BLEND, s);
+    AP_HIP(launch_lambda_grad((int32_t)N, pos, *rule, lambda, (const double*)ctx->e_ace_raw.p,
+                              (const double*)ctx->e_eam_raw.p, force, vir, s));
+  }
+  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, true, s))) return st;
+  return AP_OK;
+}
+
 ap_status ap_blend_noalloc(ap_ctx* c, const ap_systems* sys, const double* pos,
                            const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                            int32_t* n_ace, void* stream) {
@@ -1435,6 +1468,11 @@ static ap_status force_eval(Ctx* ctx, const ap_systems* sys, ap_md_state* st, hi
   if (!written) {
     AP_HIP(launch_fill_f64(st->force, 0.0, 3 * N, s));
     AP_HIP(launch_fill_f64(st->e_atom, 0.0, N, s));
+  }
+  if (st->lambda_gradient && !st->switching && ctx->has_eam && ctx->has_ace) {
+    if ((r = ap_lambda_gradient((ap_ctx*)ctx, sys, st->pos, &st->rule, st->lambda, st->force,
+                                st->virial, s)))
+      return r;
   }
   if (st->ind_K > 0) {
     if ((r = ap_indenter((ap_ctx*)ctx, sys, st->pos, st->fixed, st->ind_centre, st->ind_R, st->ind_K,

@@ -178,6 +178,7 @@ struct Ctx {
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
   Buffer sw_csp, sw_mu0, sw_mu, sw_flag, sw_src, sw_nsrc;   // dynamic switching scratch
+  Buffer e_eam_raw, e_ace_raw;          // unweighted per-atom energies of the last force calls
   int64_t cells_n_atoms = -1;           // atoms of the last neighbour build (its cell list)
   void* static_scratch = nullptr;      // this device's address of the static scratch array
   // launch mode of the mixed rank phase: forced (AP_RANK_MODE, >= 0) or tuned
@@ -266,6 +267,9 @@ hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* 
                              const double* force, const double* mass, const uint8_t* fixed,
                              double dt, bool drift, hipStream_t s);
 hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s);
+hipError_t launch_lambda_grad(int32_t n, const double* pos, const ap_lambda_rule& rule,
+                              const double* lambda, const double* e_ace, const double* e_eam,
+                              double* force, double* vir_atom, hipStream_t s);
 // dynamic switching (k_switch.hip)
 hipError_t launch_switching(const SysView& sv, const double* pos, const int32_t* nbr,
                             const int32_t* count, int32_t cap, const int32_t* cell_of,
@@ -281,7 +285,7 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* nbr,
                       const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
                       double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
-                      bool accumulate, hipStream_t s);
+                      bool accumulate, double* e_raw, hipStream_t s);
 // ACE (k_ace.hip)
 size_t ace_lds_bytes(const AceDev& a, int precision);
 hipError_t launch_ace_reset(int32_t* counter, hipStream_t s);
@@ -290,7 +294,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
-                      hipStream_t s);
+                      double* e_raw, hipStream_t s);
 // phase 0: bond basis -> A; 1: coupling/contraction/adjoint -> om, phi;
 // 2: embedding, bond gradients, virial
 hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
@@ -299,7 +303,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase, int rank_mode = AP_RANK_FUSED);
+                            int phase, int rank_mode = AP_RANK_FUSED, double* e_raw = nullptr);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 // the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
 // per L); xo: the variant that keeps X_L in LDS for both coefficient sets

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     const float* __restrict__ A_in, const float* __restrict__ om_in,
     const float* __restrict__ phi_in, float* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir) {
+    double* __restrict__ vir, double* __restrict__ e_raw) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -237,6 +237,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     if (vir)
       for (int k = 0; k < 9; ++k) vir[(int64_t)k * n + a] = w9[k];
     e_atom[a] += lam * E;
+    if (e_raw) e_raw[a] = E;
   }
 }
 
@@ -255,7 +256,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase, int rank_mode) {
+                            int phase, int rank_mode, double* e_raw) {
   const MixDev& m = c.mix;
   // grids are sized for every atom; wavefronts past *n_ace leave at once
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
@@ -317,7 +318,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
                          count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf,
-                         pair_g, e_atom, vir_atom);
+                         pair_g, e_atom, vir_atom, e_raw);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_grad<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_grad<6, 3, 6>);

@@ -104,7 +104,8 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
                                                    const double* __restrict__ wgt,
                                                    double* __restrict__ e_atom,
                                                    double* __restrict__ force,
-                                                   double* __restrict__ vir, int accumulate) {
+                                                   double* __restrict__ vir, int accumulate,
+                                                   double* __restrict__ e_raw) {
   extern __shared__ double4 tab_lds[];
   const double4* rho_c = stage_table(rho_t, tab_lds, kLds);
   const double4* phi_c = stage_table(phi_t, tab_lds + (rho_t.n - 1), kLds);
@@ -152,7 +153,9 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
     v11 -= dy * gy; v12 -= dy * gz;
     v22 -= dz * gz;
   }
-  const double e = wk > 0.0 ? wk * (eF[k] + 0.5 * ephi) : 0.0;
+  const double e_un = wk > 0.0 ? eF[k] + 0.5 * ephi : 0.0;  // E_k^EAM, unweighted
+  const double e = wk > 0.0 ? wk * e_un : 0.0;
+  if (e_raw) e_raw[k] = e_un;
   if (accumulate) {
     e_atom[k] += e;
     force[k] += fx;
@@ -175,7 +178,7 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* nbr,
                       const int32_t* count, int32_t n_atoms, const double* lambda, double* wfp,
                       double* eF, double* wgt, double* e_atom, double* force, double* vir_atom,
-                      bool accumulate, hipStream_t s) {
+                      bool accumulate, double* e_raw, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const dim3 g((n_atoms + 255) / 256), b(256);
   (void)pos;
@@ -187,7 +190,7 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
     hipLaunchKernelGGL(dens, g, b, lds ? rho_b : 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda, wfp,
                        eF, wgt);
     hipLaunchKernelGGL(frc, g, b, lds ? rho_b + phi_b : 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp,
-                       eF, wgt, e_atom, force, vir_atom, accumulate ? 1 : 0);
+                       eF, wgt, e_atom, force, vir_atom, accumulate ? 1 : 0, e_raw);
   };
   if (sv.all_ortho) {
     if (lds) go(k_eam_density<true, true>, k_eam_force<true, true>);

@@ -292,6 +292,45 @@ hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* 
   return hipGetLastError();
 }
 
+// Force of a position-dependent geometric switching parameter: atoms of the
+// cosine band (0 < lambda < 1 under rule kinds 1-3; masked and surface atoms
+// have lambda 0 or 1) get -(E^ACE - E^EAM) d lambda/d r, and their virial
+// -(r - centre) (x) (E^ACE - E^EAM) d lambda/d r (nine per-atom entries,
+// zero elsewhere, for the deterministic per-system reduction).
+__global__ void k_lambda_grad(int n, const double* __restrict__ pos, ap_lambda_rule rule,
+                              const double* __restrict__ lambda, const double* __restrict__ e_ace,
+                              const double* __restrict__ e_eam, double* __restrict__ force,
+                              double* __restrict__ vir) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lam = lambda[i];
+  const bool geo = rule.kind == AP_LAMBDA_SPHERE || rule.kind == AP_LAMBDA_HEMISPHERE ||
+                   rule.kind == AP_LAMBDA_MASK;
+  double d3[3] = {0.0, 0.0, 0.0}, g[3] = {0.0, 0.0, 0.0};
+  if (geo && lam > 0.0 && lam < 1.0) {
+    for (int k = 0; k < 3; ++k) d3[k] = pos[(int64_t)k * n + i] - rule.centre[k];
+    const double d = sqrt(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
+    const double dl = -0.5 * M_PI / rule.taper * sin(M_PI * (d - rule.r_full) / rule.taper);
+    const double c = (e_ace[i] - e_eam[i]) * dl / d;
+    for (int k = 0; k < 3; ++k) {
+      g[k] = c * d3[k];
+      force[(int64_t)k * n + i] -= g[k];
+    }
+  }
+  if (vir)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) vir[(int64_t)(3 * a + b) * n + i] = -d3[a] * g[b];
+}
+
+hipError_t launch_lambda_grad(int32_t n, const double* pos, const ap_lambda_rule& rule,
+                              const double* lambda, const double* e_ace, const double* e_eam,
+                              double* force, double* vir_atom, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lambda_grad, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, rule, lambda,
+                     e_ace, e_eam, force, vir_atom);
+  return hipGetLastError();
+}
+
 __global__ void k_check_finite(int n, const double* __restrict__ f, int32_t* __restrict__ flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
