@@ -13,6 +13,8 @@ Everything is plain, slow and written from the definitions, in float64:
 * ``geometry``  - canonical minimum-image displacement, brute-force and
   k-d-tree-candidate neighbour lists (bit-exact inclusion rule);
 * ``tables``    - evaluation of the uniform-knot piecewise-cubic EAM tables;
+* ``eam_analytic`` - the paper's W EAM in closed form (ZBL core, quintic
+  bridge, knot sums, clamped density, square-root embedding);
 * ``eam``       - EAM per-atom energy E_i = xi(sum_j zeta) + 1/2 sum_j Phi
   (paper, equation for E_i^EAM) and its gradient w.r.t. each bond vector;
 * ``ylm``       - real orthonormal spherical harmonics and their gradients;
@@ -21,7 +23,9 @@ Everything is plain, slow and written from the definitions, in float64:
 * ``ace``       - ACE atomic basis A_nlm, product basis B_v, the embedding
   E_i = phi^(1) + sqrt(|phi^(2)| + 1e-6) (paper, ACE energy equation with
   the guard at phi^(2)=0) and the chain-rule bond gradients;
-* ``switching`` - the per-atom switching parameter lambda_i (ACE weight);
+* ``switching`` - the per-atom switching parameter lambda_i (ACE weight):
+  geometric rules with their gradient, and the paper's CSP-driven dynamic
+  switching with time averages and a transition zone;
 * ``indenter``  - the spherical indenter potential V_ind and load P_ind;
 * ``ap``        - the AP blend E = sum_i [lambda_i E_i^ACE + (1-lambda_i) E_i^EAM]
   (paper, equation E_i for the AP potential, with lambda = ACE weight),

@@ -35,8 +35,13 @@ def indenter(pos, mobile, centre, R, K, direction=(0.0, 0.0, -1.0)):
 
 
 class APOracle:
-    def __init__(self, eam_tables=None, ace_model=None):
-        self.eam = EamOracle(eam_tables) if eam_tables is not None else None
+    def __init__(self, eam_tables=None, ace_model=None, eam_model=None):
+        """eam_model: an EAM object with energy_and_grad (e.g. the closed-form
+        W EAM of eam_analytic) used instead of tables."""
+        if eam_model is not None:
+            self.eam = eam_model
+        else:
+            self.eam = EamOracle(eam_tables) if eam_tables is not None else None
         self.ace = AceOracle(ace_model) if ace_model is not None else None
 
     def bond_terms(self, sysm, lam, atoms, nl):
