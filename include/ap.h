@@ -214,6 +214,32 @@ typedef struct {
   int32_t initialised;     /* [host] 0 before the first update; set to 1 by it */
 } ap_switching;
 
+/* The paper's W EAM in closed form (appendix "AP potential for tungsten":
+ * equations eam_F_Marinica, eam_Phi_Marinica, eam_rho_Marinica,
+ * tungsten_rho_up, tungsten_F_up, tungsten_Phi_up and the table of optimised
+ * parameters), evaluated in FP64 by the EAM kernels instead of tables:
+ *   xi(x)    = a_xi1 sqrt(x) + a_xi2 x^2 + d_xi   (x <= 0: a_xi2 x^2 + d_xi);
+ *   zeta(r)  = zeta_0(max(r, r_cut_rho)), zeta_0(r) = sum_i a_rho[i] (d_rho[i] - r)^3
+ *              over the knots with d_rho[i] >= r;
+ *   Phi(r)   = z^2 / (4 pi eps0 r) sum_k zbl_c[k] exp(-zbl_q[k] r / a_zbl) for
+ *              r < r_lo; sum_m b_phi[m] r^m for r_lo <= r <= r_hi; the knot sum
+ *              of (a_phi, d_phi) above r_hi.
+ * Units: eps0 in e^2/(eV A).  Pair terms end at the neighbour-list cutoff. */
+typedef struct {
+  int32_t n_phi;               /* knots of the pair sum, <= 32 */
+  const double* a_phi;         /* [host] n_phi */
+  const double* d_phi;         /* [host] n_phi */
+  int32_t n_rho;               /* knots of the density sum, <= 32 */
+  const double* a_rho;         /* [host] n_rho */
+  const double* d_rho;         /* [host] n_rho */
+  double r_cut_rho;
+  double a_xi1, a_xi2, d_xi;
+  double z, eps0, a_zbl;
+  double zbl_c[4], zbl_q[4];
+  double r_lo, r_hi;
+  double b_phi[6];
+} ap_eam_analytic;
+
 /* Create a context on HIP device `device`.  eam and/or ace may be NULL (the
  * matching force call then returns AP_ERR_ARG).  The model is copied and
  * folded into device tables; host arrays may be freed afterwards. */
@@ -237,6 +263,11 @@ ap_status ap_build_neighbors(ap_ctx* ctx, const ap_systems* sys, const double* p
 ap_status ap_blend(ap_ctx* ctx, const ap_systems* sys, const double* pos,
                    const ap_lambda_rule* rule, double* lambda, int32_t* ace_list,
                    int32_t* n_ace, void* stream);
+
+/* Use the closed-form EAM (ap_eam_analytic) in ctx instead of tables: it
+ * replaces the tables given to ap_create, or adds EAM to a context created
+ * without them.  The parameters are copied. */
+ap_status ap_set_eam_analytic(ap_ctx* ctx, const ap_eam_analytic* eam);
 
 /* Forces of a switching parameter that follows the positions (section
  * "Adaptive-precision potential": E = sum_i [lambda_i E_i^ACE + (1 - lambda_i)

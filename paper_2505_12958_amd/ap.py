@@ -65,6 +65,15 @@ class LambdaRule(C.Structure):
                 ("mask", C.c_void_p)]
 
 
+class EamAnalytic(C.Structure):
+    _fields_ = [("n_phi", C.c_int32), ("a_phi", C.POINTER(C.c_double)), ("d_phi", C.POINTER(C.c_double)),
+                ("n_rho", C.c_int32), ("a_rho", C.POINTER(C.c_double)), ("d_rho", C.POINTER(C.c_double)),
+                ("r_cut_rho", C.c_double), ("a_xi1", C.c_double), ("a_xi2", C.c_double),
+                ("d_xi", C.c_double), ("z", C.c_double), ("eps0", C.c_double), ("a_zbl", C.c_double),
+                ("zbl_c", C.c_double * 4), ("zbl_q", C.c_double * 4), ("r_lo", C.c_double),
+                ("r_hi", C.c_double), ("b_phi", C.c_double * 6)]
+
+
 class Switching(C.Structure):
     _fields_ = [("csp_lo", C.c_double), ("csp_hi", C.c_double), ("n_csp", C.c_int32),
                 ("n_csp_avg", C.c_int32), ("r_lo", C.c_double), ("r_hi", C.c_double),
@@ -118,19 +127,21 @@ def lib():
                                           C.POINTER(Switching), vp, vp, vp, vp]
         L.ap_lambda_gradient.argtypes = [vp, C.POINTER(Systems), vp, C.POINTER(LambdaRule), vp, vp,
                                          vp, vp]
+        L.ap_set_eam_analytic.argtypes = [vp, C.POINTER(EamAnalytic)]
         L.ap_check.argtypes = [vp, vp]
         L.ap_profile.argtypes = [vp, i32]
         L.ap_profile_read.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
         L.ap_info.argtypes = [vp, C.c_char_p, C.POINTER(d)]
         for f in ("ap_profile", "ap_profile_read", "ap_info", "ap_create", "ap_destroy", "ap_build_neighbors", "ap_blend", "ap_blend_noalloc",
-                  "ap_switching_update", "ap_lambda_gradient", "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
+                  "ap_switching_update", "ap_lambda_gradient", "ap_set_eam_analytic",
+                  "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step", "ap_check"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
 
 
 EXPORTS = ("ap_create", "ap_destroy", "ap_last_error", "ap_build_neighbors", "ap_blend",
-           "ap_blend_noalloc", "ap_switching_update", "ap_lambda_gradient",
+           "ap_blend_noalloc", "ap_switching_update", "ap_lambda_gradient", "ap_set_eam_analytic",
            "ap_eam_forces", "ap_ace_forces", "ap_indenter", "ap_reduce_energy", "ap_step",
            "ap_check", "ap_version", "ap_profile", "ap_profile_read", "ap_info")
 PHASES = ("neighbors", "blend", "eam", "ace", "ace_gather", "indenter", "integrate", "reduce",
@@ -279,6 +290,24 @@ class Context:
         st = lib().ap_blend(self.h, C.byref(sysarg.c), _ptr(pos), C.byref(r), _ptr(lam),
                             _ptr(ace_list), _ptr(n_ace), _stream())
         self._check(st)
+
+    def set_eam_analytic(self, p):
+        """Closed-form EAM from a parameter dict (keys as workloads.W_EAM plus
+        zbl = [(c, q)] * 4)."""
+        arrs = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("a_phi", "d_phi", "a_rho", "d_rho")}
+        e = EamAnalytic()
+        e.n_phi, e.a_phi, e.d_phi = len(arrs["a_phi"]), _dptr(arrs["a_phi"]), _dptr(arrs["d_phi"])
+        e.n_rho, e.a_rho, e.d_rho = len(arrs["a_rho"]), _dptr(arrs["a_rho"]), _dptr(arrs["d_rho"])
+        e.r_cut_rho = p["r_cut_rho"]
+        e.a_xi1, e.a_xi2 = p["a_xi"]
+        e.d_xi, e.z, e.eps0, e.a_zbl = p["d_xi"], p["Z"], p["eps0"], p["a_zbl"]
+        for k, (c, q) in enumerate(p["zbl"]):
+            e.zbl_c[k], e.zbl_q[k] = c, q
+        e.r_lo, e.r_hi = p["r_lo"], p["r_hi"]
+        for m in range(6):
+            e.b_phi[m] = p["b_phi"][m]
+        self._check(lib().ap_set_eam_analytic(self.h, C.byref(e)))
+        self.has_eam = True
 
     def lambda_gradient(self, sysarg, pos, rule, lam, force, virial=None, mask=None):
         """Add the force (and virial) of a position-dependent geometric lambda."""

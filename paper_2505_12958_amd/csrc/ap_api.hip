@@ -1340,6 +1340,51 @@ ap_status ap_switching_update(ap_ctx* c, const ap_systems* sys, const double* po
   return AP_OK;
 }
 
+ap_status ap_set_eam_analytic(ap_ctx* c, const ap_eam_analytic* e) {
+  Ctx* ctx = (Ctx*)c;
+  if (!ctx) return fail(nullptr, AP_ERR_ARG, "ctx is NULL");
+  if (!e) return fail(ctx, AP_ERR_ARG, "eam is NULL");
+  if (e->n_phi < 0 || e->n_phi > kMaxEamKnots || e->n_rho < 0 || e->n_rho > kMaxEamKnots ||
+      (e->n_phi > 0 && (!e->a_phi || !e->d_phi)) || (e->n_rho > 0 && (!e->a_rho || !e->d_rho)))
+    return fail(ctx, AP_ERR_ARG, "analytic EAM: knot arrays missing or more than 32 knots");
+  if (!(e->a_zbl > 0) || !(e->eps0 > 0) || !(e->r_lo > 0) || !(e->r_lo <= e->r_hi))
+    return fail(ctx, AP_ERR_ARG, "analytic EAM: need a_zbl, eps0 > 0 and 0 < r_lo <= r_hi");
+  EamAnalyticDev& p = ctx->ean;
+  p = EamAnalyticDev{};
+  p.n_phi = e->n_phi;
+  p.n_rho = e->n_rho;
+  for (int i = 0; i < e->n_phi; ++i) {
+    p.a_phi[i] = e->a_phi[i];
+    p.d_phi[i] = e->d_phi[i];
+  }
+  for (int i = 0; i < e->n_rho; ++i) {
+    p.a_rho[i] = e->a_rho[i];
+    p.d_rho[i] = e->d_rho[i];
+  }
+  p.r_cut_rho = e->r_cut_rho;
+  double zc = 0.0;
+  for (int i = 0; i < e->n_rho; ++i) {
+    const double t = e->d_rho[i] - e->r_cut_rho;
+    if (t >= 0.0) zc += e->a_rho[i] * t * t * t;
+  }
+  p.zeta_cut = zc;
+  p.a_xi1 = e->a_xi1;
+  p.a_xi2 = e->a_xi2;
+  p.d_xi = e->d_xi;
+  p.zbl_pref = e->z * e->z / (4.0 * M_PI * e->eps0);
+  p.a_zbl = e->a_zbl;
+  for (int k = 0; k < 4; ++k) {
+    p.zbl_c[k] = e->zbl_c[k];
+    p.zbl_q[k] = e->zbl_q[k];
+  }
+  p.r_lo = e->r_lo;
+  p.r_hi = e->r_hi;
+  for (int m = 0; m < 6; ++m) p.b_phi[m] = e->b_phi[m];
+  ctx->eam_analytic = true;
+  ctx->has_eam = true;
+  return AP_OK;
+}
+
 ap_status ap_lambda_gradient(ap_ctx* c, const ap_systems* sys, const double* pos,
                              const ap_lambda_rule* rule, const double* lambda, double* force,
                              double* virial, void* stream) {

@@ -52,6 +52,19 @@ struct TableDev {
   const float* cf;          // same, float
 };
 
+// the paper's W EAM in closed form (passed to the EAM kernels by value)
+constexpr int kMaxEamKnots = 32;
+struct EamAnalyticDev {
+  int32_t n_phi, n_rho;
+  double a_phi[kMaxEamKnots], d_phi[kMaxEamKnots];
+  double a_rho[kMaxEamKnots], d_rho[kMaxEamKnots];
+  double r_cut_rho, zeta_cut;       // zeta = zeta_0(max(r, r_cut)); zeta_cut = zeta_0(r_cut)
+  double a_xi1, a_xi2, d_xi;
+  double zbl_pref, a_zbl;           // Z^2 / (4 pi eps0), screening length
+  double zbl_c[4], zbl_q[4];
+  double r_lo, r_hi, b_phi[6];
+};
+
 // ACE model folded for the device
 // one term of the FP64 path's sparse sums, read as a single 16-byte load:
 // coefficient c and the two operand indices i, j
@@ -162,6 +175,8 @@ struct Ctx {
   std::string err;
   bool has_eam = false, has_ace = false;
   TableDev phi{}, rho{}, F{};
+  bool eam_analytic = false;            // EAM in closed form (ean) instead of the tables
+  EamAnalyticDev ean{};
   AceDev ace{};
   MixDev mix{};
   std::vector<Buffer> owned;            // model tables

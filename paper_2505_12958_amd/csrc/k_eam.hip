@@ -32,6 +32,61 @@ __device__ __forceinline__ void tab_eval(const TableDev& t, const double4* coef,
   }
 }
 
+// ---- the paper's W EAM in closed form (appendix "AP potential for tungsten":
+// equations eam_F_Marinica, eam_Phi_Marinica, eam_rho_Marinica,
+// tungsten_rho_up, tungsten_F_up, tungsten_Phi_up), FP64.
+__device__ __forceinline__ void an_knots(const double* a, const double* d, int n, double r, double& v,
+                                         double& dv) {
+  v = 0.0;
+  dv = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double t = d[i] - r;
+    if (t >= 0.0) {
+      const double t2 = t * t;
+      v += a[i] * t2 * t;
+      dv -= 3.0 * a[i] * t2;
+    }
+  }
+}
+
+// zeta(r) = zeta_0(max(r, r_cut))
+__device__ __forceinline__ void an_density(const EamAnalyticDev& p, double r, double& v, double& dv) {
+  if (r <= p.r_cut_rho) {
+    v = p.zeta_cut;
+    dv = 0.0;
+  } else {
+    an_knots(p.a_rho, p.d_rho, p.n_rho, r, v, dv);
+  }
+}
+
+// Phi^Fit(r): screened Coulomb below r_lo, quintic bridge up to r_hi, knot sum above
+__device__ __forceinline__ void an_pair(const EamAnalyticDev& p, double r, double& v, double& dv) {
+  if (r < p.r_lo) {
+    const double x = r / p.a_zbl;
+    double s = 0.0, ds = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const double e = exp(-p.zbl_q[k] * x);
+      s += p.zbl_c[k] * e;
+      ds -= p.zbl_c[k] * p.zbl_q[k] / p.a_zbl * e;
+    }
+    v = p.zbl_pref * s / r;
+    dv = p.zbl_pref * (ds / r - s / (r * r));
+  } else if (r <= p.r_hi) {
+    const double* b = p.b_phi;
+    v = b[0] + r * (b[1] + r * (b[2] + r * (b[3] + r * (b[4] + r * b[5]))));
+    dv = b[1] + r * (2.0 * b[2] + r * (3.0 * b[3] + r * (4.0 * b[4] + r * 5.0 * b[5])));
+  } else {
+    an_knots(p.a_phi, p.d_phi, p.n_phi, r, v, dv);
+  }
+}
+
+// xi^Fit(x) = a1 sqrt(x) + a2 x^2 + Delta xi (the square root dropped for x <= 0)
+__device__ __forceinline__ void an_embed(const EamAnalyticDev& p, double x, double& v, double& dv) {
+  const double s = x > 0.0 ? sqrt(x) : 0.0;
+  v = p.a_xi1 * s + p.a_xi2 * x * x + p.d_xi;
+  dv = (x > 0.0 ? 0.5 * p.a_xi1 / s : 0.0) + 2.0 * p.a_xi2 * x;
+}
+
 // Copies a table's coefficients into LDS (whole workgroup, before any thread
 // leaves); returns where the bond loop reads them from.
 __device__ __forceinline__ const double4* stage_table(const TableDev& t, double4* lds, bool use) {
@@ -44,8 +99,9 @@ __device__ __forceinline__ const double4* stage_table(const TableDev& t, double4
 // kOrtho: every system is orthorhombic, so the box edges are hoisted out of
 // the bond loop (same arithmetic as the general displacement).  kLds: the
 // pair tables are staged in LDS (dynamic shared memory sized by the host).
-template <bool kOrtho, bool kLds>
+template <bool kOrtho, bool kLds, bool kAn>
 __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t, TableDev F_t,
+                                                     EamAnalyticDev an,
                                                      const double4* __restrict__ pos4,
                                                      const int32_t* __restrict__ nbr,
                                                      const int32_t* __restrict__ count,
@@ -85,17 +141,20 @@ __global__ __launch_bounds__(256) void k_eam_density(SysView sv, TableDev rho_t,
       displacement(ortho, H, Hi, sv.per, pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, dx, dy, dz);
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     double v, dv;
-    tab_eval(rho_t, rho_c, r, false, v, dv);
+    if constexpr (kAn) an_density(an, r, v, dv);
+    else tab_eval(rho_t, rho_c, r, false, v, dv);
     rho += v;
   }
   double Fv, Fp;
-  tab_eval(F_t, reinterpret_cast<const double4*>(F_t.c), rho, true, Fv, Fp);
+  if constexpr (kAn) an_embed(an, rho, Fv, Fp);
+  else tab_eval(F_t, reinterpret_cast<const double4*>(F_t.c), rho, true, Fv, Fp);
   wfp[i] = w * Fp;
   eF[i] = Fv;
 }
 
-template <bool kOrtho, bool kLds>
+template <bool kOrtho, bool kLds, bool kAn>
 __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, TableDev phi_t,
+                                                   EamAnalyticDev an,
                                                    const double4* __restrict__ pos4,
                                                    const int32_t* __restrict__ nbr,
                                                    const int32_t* __restrict__ count,
@@ -139,8 +198,13 @@ __global__ __launch_bounds__(256) void k_eam_force(SysView sv, TableDev rho_t, T
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double ir = 1.0 / r;
     double z, dzr, p, dp;
-    tab_eval(rho_t, rho_c, r, false, z, dzr);
-    tab_eval(phi_t, phi_c, r, false, p, dp);
+    if constexpr (kAn) {
+      an_density(an, r, z, dzr);
+      an_pair(an, r, p, dp);
+    } else {
+      tab_eval(rho_t, rho_c, r, false, z, dzr);
+      tab_eval(phi_t, phi_c, r, false, p, dp);
+    }
     const double a = ((fk + fj) * dzr + 0.5 * (wk + wj) * dp) * ir;
     fx += a * dx;
     fy += a * dy;
@@ -184,20 +248,24 @@ hipError_t launch_eam(const Ctx& c, const SysView& sv, const double* pos, const 
   (void)pos;
   // pair tables in LDS when both fit in a quarter of a CU's LDS (four
   // resident workgroups); otherwise they are read through the caches
-  const size_t rho_b = 32 * (size_t)(c.rho.n - 1), phi_b = 32 * (size_t)(c.phi.n - 1);
-  const bool lds = rho_b + phi_b <= 40 * 1024;
+  const size_t rho_b = c.eam_analytic ? 0 : 32 * (size_t)(c.rho.n - 1);
+  const size_t phi_b = c.eam_analytic ? 0 : 32 * (size_t)(c.phi.n - 1);
+  const bool lds = !c.eam_analytic && rho_b + phi_b <= 40 * 1024;
   auto go = [&](auto dens, auto frc) {
-    hipLaunchKernelGGL(dens, g, b, lds ? rho_b : 0, s, sv, c.rho, c.F, pos4, nbr, count, lambda, wfp,
-                       eF, wgt);
-    hipLaunchKernelGGL(frc, g, b, lds ? rho_b + phi_b : 0, s, sv, c.rho, c.phi, pos4, nbr, count, wfp,
-                       eF, wgt, e_atom, force, vir_atom, accumulate ? 1 : 0, e_raw);
+    hipLaunchKernelGGL(dens, g, b, lds ? rho_b : 0, s, sv, c.rho, c.F, c.ean, pos4, nbr, count, lambda,
+                       wfp, eF, wgt);
+    hipLaunchKernelGGL(frc, g, b, lds ? rho_b + phi_b : 0, s, sv, c.rho, c.phi, c.ean, pos4, nbr, count,
+                       wfp, eF, wgt, e_atom, force, vir_atom, accumulate ? 1 : 0, e_raw);
   };
-  if (sv.all_ortho) {
-    if (lds) go(k_eam_density<true, true>, k_eam_force<true, true>);
-    else go(k_eam_density<true, false>, k_eam_force<true, false>);
+  if (c.eam_analytic) {
+    if (sv.all_ortho) go(k_eam_density<true, false, true>, k_eam_force<true, false, true>);
+    else go(k_eam_density<false, false, true>, k_eam_force<false, false, true>);
+  } else if (sv.all_ortho) {
+    if (lds) go(k_eam_density<true, true, false>, k_eam_force<true, true, false>);
+    else go(k_eam_density<true, false, false>, k_eam_force<true, false, false>);
   } else {
-    if (lds) go(k_eam_density<false, true>, k_eam_force<false, true>);
-    else go(k_eam_density<false, false>, k_eam_force<false, false>);
+    if (lds) go(k_eam_density<false, true, false>, k_eam_force<false, true, false>);
+    else go(k_eam_density<false, false, false>, k_eam_force<false, false, false>);
   }
   return hipGetLastError();
 }

@@ -6,7 +6,7 @@ from paper_2505_12958_amd import ap
 
 
 def run_force(wl, precision=ap.AP_PREC_FP64, capacity=64, lam=None, with_eam=True, with_ace=True,
-              virial=True, pos=None, with_rev=True):
+              virial=True, pos=None, with_rev=True, eam_analytic=None):
     """One AP force evaluation on the GPU: blend (unless lam given), neighbours,
     EAM, ACE.  Returns host numpy arrays."""
     dev = "cuda"
@@ -14,7 +14,10 @@ def run_force(wl, precision=ap.AP_PREC_FP64, capacity=64, lam=None, with_eam=Tru
     S = ap.SystemsArg.from_workload(wl)
     p = wl.pos if pos is None else pos
     P = torch.tensor(np.ascontiguousarray(p.T), dtype=torch.float64, device=dev)
-    ctx = ap.Context(wl.eam if with_eam else None, wl.ace if with_ace else None, precision)
+    ctx = ap.Context(wl.eam if with_eam and eam_analytic is None else None,
+                     wl.ace if with_ace else None, precision)
+    if with_eam and eam_analytic is not None:
+        ctx.set_eam_analytic(eam_analytic)
     nl = ap.NeighbourList(N, capacity, dev, with_rev)
     ctx.build_neighbors(S, P, nl)
     lam_t = torch.zeros(N, dtype=torch.float64, device=dev)
