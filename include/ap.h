@@ -43,9 +43,15 @@
  * ap_step with check_every > 0).  An asynchronous HIP fault surfaces as
  * AP_ERR_HIP from the next call that synchronises.
  *
- * Determinism: no floating-point atomics anywhere; forces are gathered with
- * a reverse-slot index and every sum has a fixed order, so FP64 results are
- * bitwise reproducible run to run.
+ * Determinism: the FP64 path has no floating-point atomics; forces are
+ * gathered with a reverse-slot index and every sum has a fixed order, so its
+ * results are bitwise reproducible run to run.  The mixed path adds the
+ * partial sums of each atom's phi_p (a handful per atom) with FP32 atomic
+ * adds in LDS, so its energies and forces may differ in the last FP32 bits
+ * between runs (far inside its 1e-5 tolerance); everything else there has a
+ * fixed order.  Integer atomics (work queues, cell counts, overflow maxima,
+ * the switching spread's maximum over FP64 bit patterns of non-negative
+ * values) do not affect results.
  */
 #ifndef AP_H
 #define AP_H
@@ -368,12 +374,25 @@ typedef struct {
                              (after the neighbour build) instead of `rule` */
   int32_t lambda_gradient;/* nonzero (geometric rule, EAM and ACE): forces include the
                              term of ap_lambda_gradient */
+  const uint8_t* nvt;     /* [n_atoms] or NULL: nonzero marks the atoms of the Nose-Hoover layer
+                             (section "Nanoindentation"); an atom also marked fixed stays fixed
+                             and is not counted */
+  double nvt_T;           /* layer target temperature, K (> 0 when nvt is set) */
+  double nvt_tau;         /* thermostat time constant, fs (> 0 when nvt is set) */
+  double* nvt_xi;         /* [n_systems][2] device, caller-owned: the thermostat rate xi (1/fs)
+                             and its time integral eta; zero them before the first step.  The
+                             conserved quantity is K + U + 3 n_layer k_B T0 (tau^2 xi^2/2 + eta). */
 } ap_md_state;
 
 /* n_steps == 0: one force evaluation at the current positions
  * (blend, neighbours, EAM, ACE, indenter, reductions).  n_steps > 0:
  * velocity-Verlet steps (half kick, drift with periodic wrap, indenter move,
  * force evaluation, half kick; fixed atoms never move and keep v = 0).
+ * With a Nose-Hoover layer (st->nvt) each step is thermostat(dt/2), kick,
+ * drift, forces, kick, thermostat(dt/2), one thermostat per system: its half
+ * step advances xi by dt/4 (T/T0 - 1)/tau^2, eta by xi dt/2, scales the
+ * layer's velocities by exp(-xi dt/2) and advances xi again with the scaled
+ * temperature T = sum m v^2 / (3 n_layer k_B) (deterministic sums).
  * The forces in st->force must be those of the current positions when
  * n_steps > 0 (call once with n_steps = 0 first). */
 ap_status ap_step(ap_ctx* ctx, const ap_systems* sys, ap_md_state* st, int32_t n_steps,

@@ -26,11 +26,14 @@ Everything is plain, slow and written from the definitions, in float64:
 * ``switching`` - the per-atom switching parameter lambda_i (ACE weight):
   geometric rules with their gradient, and the paper's CSP-driven dynamic
   switching with time averages and a transition zone;
-* ``indenter``  - the spherical indenter potential V_ind and load P_ind;
 * ``ap``        - the AP blend E = sum_i [lambda_i E_i^ACE + (1-lambda_i) E_i^EAM]
   (paper, equation E_i for the AP potential, with lambda = ACE weight),
-  forces -dE/dr at fixed lambda, and the virial;
-* ``md``        - FP64 velocity-Verlet.
+  forces -dE/dr at fixed lambda (plus the grad-lambda term of a geometric
+  rule), the virial, and the spherical indenter V_ind with its load P_ind;
+* ``md``        - FP64 velocity-Verlet with fixed atoms and the Nose-Hoover
+  layer of the nanoindentation protocol (and its conserved extended energy);
+* ``indentation`` - depth, Hertzian load and its fit for E*, contact radius
+  and hardness of a load curve.
 
 Pins (tests marked "not gpu") tie each function to what the paper or the
 mathematics fixes; see the test files for each pin.  The synthetic ACE model

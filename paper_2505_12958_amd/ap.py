@@ -91,7 +91,9 @@ class MDState(C.Structure):
                 ("ind_dir", C.c_double * 3), ("ind_R", C.c_double), ("ind_K", C.c_double),
                 ("virial", C.c_void_p), ("e_sys", C.c_void_p), ("e_ind", C.c_void_p),
                 ("load", C.c_void_p), ("check_every", C.c_int32),
-                ("switching", C.POINTER(Switching)), ("lambda_gradient", C.c_int32)]
+                ("switching", C.POINTER(Switching)), ("lambda_gradient", C.c_int32),
+                ("nvt", C.c_void_p), ("nvt_T", C.c_double), ("nvt_tau", C.c_double),
+                ("nvt_xi", C.c_void_p)]
 
 
 _lib = None
@@ -423,9 +425,23 @@ class MD:
         c.check_every = 0
         c.switching = None
         c.lambda_gradient = 0
+        c.nvt, c.nvt_T, c.nvt_tau, c.nvt_xi = None, 0.0, 0.0, None
         self.c = c
         self.switching = None
+        self.nvt = None
+        self.nvt_xi = None
         self.ind_centre = np.array(c.ind_centre[:])
+        self._device = device
+        self._n_sys = wl.n_systems
+
+    def use_nvt(self, layer, T, tau):
+        """Nose-Hoover thermostat at temperature T (K) with time constant tau
+        (fs) on the atoms where `layer` (N booleans) is true; xi and eta
+        start at zero (self.nvt_xi, [n_systems][2])."""
+        self.nvt = torch.tensor(np.asarray(layer, dtype=np.uint8), device=self._device)
+        self.nvt_xi = torch.zeros((self._n_sys, 2), dtype=torch.float64, device=self._device)
+        self.c.nvt, self.c.nvt_xi = self.nvt.data_ptr(), self.nvt_xi.data_ptr()
+        self.c.nvt_T, self.c.nvt_tau = float(T), float(tau)
 
     def use_switching(self, sw):
         """Take lambda from the dynamic switching rule sw (DynamicSwitching)

@@ -990,7 +990,7 @@ ap_status ap_destroy(ap_ctx* c) {
                     &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn, &ctx->sw_csp, &ctx->sw_mu0,
                     &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc,
-                    &ctx->e_eam_raw, &ctx->e_ace_raw})
+                    &ctx->e_eam_raw, &ctx->e_ace_raw, &ctx->nvt_ke, &ctx->nvt_sums, &ctx->nvt_fac})
     release(*b);
   delete ctx;
   return AP_OK;
@@ -1540,21 +1540,49 @@ ap_status ap_step(ap_ctx* c, const ap_systems* sys, ap_md_state* st, int32_t n_s
   SysView sv;
   if ((r = prepare_systems(ctx, sys, &sv))) return r;
   const int64_t N = sv.n_atoms;
+  const bool nvt = st->nvt != nullptr && n_steps > 0;
+  if (nvt) {
+    if (!(st->nvt_T > 0) || !(st->nvt_tau > 0) || !st->nvt_xi)
+      return fail(ctx, AP_ERR_ARG, "Nose-Hoover layer needs nvt_T > 0, nvt_tau > 0 and nvt_xi");
+    if ((r = ensure(ctx, ctx->nvt_ke, 16 * (size_t)std::max<int64_t>(N, 1))) ||
+        (r = ensure(ctx, ctx->nvt_sums, 16 * (size_t)sv.n_sys)) ||
+        (r = ensure(ctx, ctx->nvt_fac, 8 * (size_t)sv.n_sys)))
+      return r;
+  }
+  double* nvt_sums = (double*)ctx->nvt_sums.p;
+  double* nvt_fac = (double*)ctx->nvt_fac.p;
+  // layer sums of m v^2 and atom counts of the current velocities
+  auto layer_sums = [&]() -> ap_status {
+    {
+      PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
+      AP_HIP(launch_nvt_ke((int32_t)N, st->vel, st->mass, st->nvt, st->fixed, (double*)ctx->nvt_ke.p, s));
+    }
+    return reduce_into(ctx, sv, (const double*)ctx->nvt_ke.p, 2, nvt_sums, false, s);
+  };
   if (n_steps == 0) {
     if ((r = force_eval(ctx, sys, st, s))) return r;
   }
+  if (nvt && (r = layer_sums())) return r;
   for (int step = 0; step < n_steps; ++step) {
     {
       PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
+      if (nvt) AP_HIP(launch_nvt_half(sv.n_sys, nvt_sums, st->nvt_xi, nvt_fac, st->nvt_T, st->nvt_tau,
+                                      st->dt, s));
       AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed,
-                               st->dt, true, s));
+                               st->nvt, nvt ? nvt_fac : nullptr, st->dt, true, s));
     }
     for (int k = 0; k < 3; ++k) st->ind_centre[k] += st->dt * st->ind_vel[k];
     if ((r = force_eval(ctx, sys, st, s))) return r;
     {
       PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
       AP_HIP(launch_kick_drift((int32_t)N, sv, st->pos, st->vel, st->force, st->mass, st->fixed,
-                               st->dt, false, s));
+                               nullptr, nullptr, st->dt, false, s));
+    }
+    if (nvt) {
+      if ((r = layer_sums())) return r;
+      PhaseTimer timer(ctx, AP_PHASE_INTEGRATE, s);
+      AP_HIP(launch_nvt_half(sv.n_sys, nvt_sums, st->nvt_xi, nvt_fac, st->nvt_T, st->nvt_tau, st->dt, s));
+      AP_HIP(launch_nvt_scale((int32_t)N, sv, st->vel, st->nvt, st->fixed, nvt_fac, s));
     }
     if (st->check_every > 0 && (step + 1) % st->check_every == 0) {
       AP_HIP(launch_check_finite((int32_t)N, st->force, (int32_t*)ctx->flags.p + 1, s));

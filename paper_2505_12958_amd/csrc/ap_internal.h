@@ -192,6 +192,7 @@ struct Ctx {
   Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
   Buffer partials, flags;               // flags: [0] nbr overflow max count, [1] nonfinite
   Buffer ind_atom;
+  Buffer nvt_ke, nvt_sums, nvt_fac;      // Nose-Hoover layer: per-atom m v^2, per-system sums, scale
   Buffer sw_csp, sw_mu0, sw_mu, sw_flag, sw_src, sw_nsrc;   // dynamic switching scratch
   Buffer e_eam_raw, e_ace_raw;          // unweighted per-atom energies of the last force calls
   int64_t cells_n_atoms = -1;           // atoms of the last neighbour build (its cell list)
@@ -280,7 +281,14 @@ hipError_t launch_indenter(int32_t n, const double* pos, const uint8_t* fixed, c
                            hipStream_t s);
 hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* vel,
                              const double* force, const double* mass, const uint8_t* fixed,
-                             double dt, bool drift, hipStream_t s);
+                             const uint8_t* nvt, const double* nvt_fac, double dt, bool drift,
+                             hipStream_t s);
+hipError_t launch_nvt_ke(int32_t n, const double* vel, const double* mass, const uint8_t* nvt,
+                         const uint8_t* fixed, double* out, hipStream_t s);
+hipError_t launch_nvt_half(int32_t n_sys, double* sums, double* xi, double* fac, double T0,
+                           double tau, double dt, hipStream_t s);
+hipError_t launch_nvt_scale(int32_t n, const SysView& sv, double* vel, const uint8_t* nvt,
+                            const uint8_t* fixed, const double* fac, hipStream_t s);
 hipError_t launch_check_finite(int32_t n, const double* force, int32_t* flag, hipStream_t s);
 hipError_t launch_lambda_grad(int32_t n, const double* pos, const ap_lambda_rule& rule,
                               const double* lambda, const double* e_ace, const double* e_eam,

@@ -254,10 +254,12 @@ hipError_t launch_indenter(int32_t n, const double* pos, const uint8_t* fixed, c
 // --------------------------------------------------------------------------
 // velocity Verlet: half kick, optional drift with periodic wrap
 constexpr double kAcc = 9.648533212e-3;  // (eV/A/amu) -> A/fs^2
+constexpr double kKb = 8.617333262e-5;   // Boltzmann constant, eV/K
 
 __global__ void k_kick_drift(int n, SysView sv, double* __restrict__ pos, double* __restrict__ vel,
                              const double* __restrict__ force, const double* __restrict__ mass,
-                             const uint8_t* __restrict__ fixed, double dt, int drift) {
+                             const uint8_t* __restrict__ fixed, const uint8_t* __restrict__ nvt,
+                             const double* __restrict__ nvt_fac, double dt, int drift) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (fixed && fixed[i]) {
@@ -269,8 +271,10 @@ __global__ void k_kick_drift(int n, SysView sv, double* __restrict__ pos, double
   const double a = 0.5 * dt * kAcc / mass[i];
   const int s = sv.sys_of[i];
   const double* H = sv.H + 9 * s;
+  // thermostat scaling of the layer's velocities, applied before the kick
+  const double f = (nvt_fac && nvt[i]) ? nvt_fac[s] : 1.0;
   for (int k = 0; k < 3; ++k) {
-    double v = vel[k * n + i] + a * force[k * n + i];
+    double v = f * vel[k * n + i] + a * force[k * n + i];
     vel[k * n + i] = v;
     if (drift) {
       double x = pos[k * n + i] + dt * v;
@@ -285,10 +289,89 @@ __global__ void k_kick_drift(int n, SysView sv, double* __restrict__ pos, double
 
 hipError_t launch_kick_drift(int32_t n, const SysView& sv, double* pos, double* vel,
                              const double* force, const double* mass, const uint8_t* fixed,
-                             double dt, bool drift, hipStream_t s) {
+                             const uint8_t* nvt, const double* nvt_fac, double dt, bool drift,
+                             hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_kick_drift, dim3((n + 255) / 256), dim3(256), 0, s, n, sv, pos, vel, force,
-                     mass, fixed, dt, drift ? 1 : 0);
+                     mass, fixed, nvt, nvt_fac, dt, drift ? 1 : 0);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Nose-Hoover layer (section "Nanoindentation": the NVT region between the
+// fixed bottom and the NVE top).  Per system s: xi_s, its integral eta_s, and
+// dv/dt = F/m - xi_s v on the layer's atoms with dxi/dt = (T/T0 - 1)/tau^2.
+
+// out[i] = m v^2 of a (non-fixed) layer atom, out[n + i] = 1 for it; zero
+// elsewhere (reduced per system in a fixed order).
+__global__ void k_nvt_ke(int n, const double* __restrict__ vel, const double* __restrict__ mass,
+                         const uint8_t* __restrict__ nvt, const uint8_t* __restrict__ fixed,
+                         double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool on = nvt[i] && !(fixed && fixed[i]);
+  const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+  out[i] = on ? mass[i] * (vx * vx + vy * vy + vz * vz) : 0.0;
+  out[n + i] = on ? 1.0 : 0.0;
+}
+
+// Half a thermostat step per system: xi += dt/4 G(T), eta += xi dt/2,
+// f = exp(-xi dt/2), T *= f^2, xi += dt/4 G(T).  sums[2s] holds the layer's
+// sum of m v^2 (updated to the scaled value), sums[2s + 1] its atom count.
+__global__ void k_nvt_half(int n_sys, double* __restrict__ sums, double* __restrict__ xi,
+                           double* __restrict__ fac, double T0, double tau, double dt) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sys) return;
+  const double cnt = sums[2 * s + 1];
+  if (!(cnt > 0.0)) {
+    fac[s] = 1.0;
+    return;
+  }
+  const double gkt = 3.0 * cnt * kKb * T0;       // g k_B T0, eV
+  const double c = 0.25 * dt / (tau * tau);
+  double twok = sums[2 * s] / kAcc;              // 2K, eV
+  double x = xi[2 * s];
+  x += c * (twok / gkt - 1.0);
+  const double eta = xi[2 * s + 1] + 0.5 * dt * x;
+  const double f = exp(-0.5 * dt * x);
+  twok *= f * f;
+  x += c * (twok / gkt - 1.0);
+  xi[2 * s] = x;
+  xi[2 * s + 1] = eta;
+  fac[s] = f;
+  sums[2 * s] = twok * kAcc;
+}
+
+__global__ void k_nvt_scale(int n, const int32_t* __restrict__ sys_of, double* __restrict__ vel,
+                            const uint8_t* __restrict__ nvt, const uint8_t* __restrict__ fixed,
+                            const double* __restrict__ fac) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !nvt[i] || (fixed && fixed[i])) return;
+  const double f = fac[sys_of[i]];
+  vel[i] *= f;
+  vel[n + i] *= f;
+  vel[2 * n + i] *= f;
+}
+
+hipError_t launch_nvt_ke(int32_t n, const double* vel, const double* mass, const uint8_t* nvt,
+                         const uint8_t* fixed, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nvt_ke, dim3((n + 255) / 256), dim3(256), 0, s, n, vel, mass, nvt, fixed, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nvt_half(int32_t n_sys, double* sums, double* xi, double* fac, double T0,
+                           double tau, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_nvt_half, dim3((n_sys + 63) / 64), dim3(64), 0, s, n_sys, sums, xi, fac, T0,
+                     tau, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_nvt_scale(int32_t n, const SysView& sv, double* vel, const uint8_t* nvt,
+                            const uint8_t* fixed, const double* fac, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nvt_scale, dim3((n + 255) / 256), dim3(256), 0, s, n, sv.sys_of, vel, nvt,
+                     fixed, fac);
   return hipGetLastError();
 }
 

@@ -346,6 +346,7 @@ class Workload:
     dt: float = 2.0
     steps: int = 0
     meta: dict = field(default_factory=dict)
+    nvt: np.ndarray | None = None  # (N,) bool: Nose-Hoover layer (None: none)
 
     @property
     def n_atoms(self):
@@ -453,6 +454,71 @@ def make_slab(name, lattice, ncell, a, kind, seed, *, n_max, l_max, nu_max, n0, 
                     periodic=(True, True, False), cutoff=CUTOFF, masses=masses, fixed=fixed,
                     vel=vel, eam=eam, ace=ace, rule=rule, indenter=ind, dt=dt, steps=steps,
                     meta=dict(z_top=z_top, lattice=lattice, a=a, ncell=tuple(ncell)))
+
+
+# The paper's nanoindentation set-ups (tables of simulation parameters for
+# W and Cu in section "Results"; thermostat time constant from step 4 of the
+# equilibration table).  Lengths A, times fs, velocities A/fs
+# (20 m/s = 2e-4 A/fs), k_ind eV/A^3.
+INDENT_W = dict(lattice="bcc", a=A_W, mass=MASS_W, n_cells=86, T=300.0, h_fixed=20.0, h_nvt=10.0,
+                dt=1.0, R=60.0, speed=2.0e-4, K=236.0, h_max=20.8, h0=-4.2, tau=100.0)
+W_EAM_A0 = 3.1837                 # lattice constant of the paper's W EAM (properties table, EAM fit)
+INDENT_CU = dict(lattice="fcc", a=A_CU, mass=MASS_CU, n_cells=100, T=292.0, h_fixed=10.0,
+                 h_nvt=10.0, dt=1.0, R=60.0, speed=2.5e-4, K=10.0, h_max=20.0, h0=-5.0, tau=100.0)
+
+
+def make_indentation(setup, *, n_cells=None, a=None, seed=7, vacuum=30.0, eam=None, ace=None,
+                     rule=None):
+    """Slab of the paper's nanoindentation set-up: an (100) surface on top,
+    periodic in x and y, the bottom h_fixed A fixed, the next h_nvt A the
+    Nose-Hoover layer, the rest NVE; Maxwell velocities at T on the mobile
+    atoms; the spherical indenter above the centre of the surface with its
+    lowest point h0 above the top atomic plane, moving down at `speed`.
+    n_cells (default: the paper's box, 86 cells of W = 1,272,112 atoms, 100
+    cells of Cu = 4,000,000 atoms) sets the cube edge in unit cells; a
+    (default the set-up's) is the lattice constant, which should be the
+    potential's own so that the slab starts at its equilibrium density.  The
+    potential (eam, ace, rule) is the caller's; rule defaults to lambda = 0
+    (EAM everywhere)."""
+    p = setup
+    n = p["n_cells"] if n_cells is None else n_cells
+    a = p["a"] if a is None else float(a)
+    pos = lattice_points(p["lattice"], (n, n, n), a)
+    N = len(pos)
+    L = n * a
+    z_top = float(pos[:, 2].max())
+    z0 = float(pos[:, 2].min())
+    fixed = (pos[:, 2] < z0 + p["h_fixed"]).astype(np.uint8)
+    nvt = (fixed == 0) & (pos[:, 2] < z0 + p["h_fixed"] + p["h_nvt"])
+    masses = np.full(N, p["mass"])
+    vel = maxwell(np.random.default_rng(seed), masses, fixed == 0, p["T"])
+    centre = np.array([L / 2, L / 2, z_top + p["R"] - p["h0"]])
+    ind = dict(centre=centre, vel=np.array([0.0, 0.0, -p["speed"]]), R=p["R"], K=p["K"])
+    box = np.diag([L, L, n * a + vacuum + p["R"]])[None].astype(np.float64)
+    if rule is None:
+        rule = LambdaRule(LAMBDA_CONST, value=0.0)
+    return Workload(name=f"indent-{p['lattice']}-{n}", pos=pos, box=box,
+                    sys_offset=np.array([0, N], np.int64), periodic=(True, True, False),
+                    cutoff=CUTOFF, masses=masses, fixed=fixed, vel=vel, eam=eam, ace=ace, rule=rule,
+                    indenter=ind, dt=p["dt"], steps=0, nvt=nvt,
+                    meta=dict(z_top=z_top, lattice=p["lattice"], a=a, ncell=(n, n, n),
+                              setup=dict(p, a=a)))
+
+
+def make_crystal(lattice, ncell, a, mass, T, seed=0):
+    """Perfect fully periodic cube of ncell^3 unit cells with Maxwell
+    velocities at T; lambda = 0 everywhere, no potential attached."""
+    pos = lattice_points(lattice, (ncell,) * 3, a)
+    n = len(pos)
+    L = ncell * a
+    masses = np.full(n, mass)
+    vel = maxwell(np.random.default_rng(seed), masses, np.ones(n, bool), T)
+    return Workload(name=f"{lattice}-crystal-{ncell}", pos=pos,
+                    box=np.diag([L, L, L])[None].astype(np.float64),
+                    sys_offset=np.array([0, n], np.int64), periodic=(True, True, True),
+                    cutoff=CUTOFF, masses=masses, fixed=np.zeros(n, np.uint8), vel=vel, eam=None,
+                    ace=None, rule=LambdaRule(LAMBDA_CONST, value=0.0), indenter=dict(K=0.0), dt=1.0,
+                    steps=0, meta=dict(lattice=lattice, a=a, ncell=(ncell,) * 3))
 
 
 def make_bulk(name, ncell, a, seed, *, n_max, l_max, nu_max, jitter=0.05, r_full=10.0,
