@@ -60,6 +60,10 @@ def parse():
     p.add_argument("--pmc-probe", action="store_true",
                    help="for rocprofv3 --pmc runs: a 256 MiB elementwise kernel (counter "
                         "calibration), then three mixed force evaluations; prints nothing else")
+    p.add_argument("--probe-key", default=None,
+                   help="with --pmc-probe: write the workload key (name, mode, ACE atoms) here")
+    p.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KEY_JSON", "OUT"),
+                   help="write the rank kernels' HBM traffic record from two --pmc runs of the probe")
     return p.parse_args()
 
 
@@ -237,12 +241,70 @@ def roofline_model(ctx, ap, wl, n_ace, n_bonds, n_bonds_ace, fp64):
     return ph
 
 
+TRAFFIC_SOURCES = ["paper_2505_12958_amd/csrc/ace_rank.h", "paper_2505_12958_amd/csrc/k_ace_rank.hip",
+                   "paper_2505_12958_amd/csrc/ap_internal.h", "paper_2505_12958_amd/csrc/ap_api.hip"]
+COPY_BYTES = 256 * 1024 * 1024        # the probe's elementwise kernel reads and writes 256 MiB
+
+
+def sources_sha256(paths):
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for src in paths:
+        with open(os.path.join(here, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def record_traffic(fetch_csv, write_csv, key_json, out):
+    """HBM bytes of one pass of the per-rank kernels from two rocprofv3 --pmc
+    runs of `bench.py --pmc-probe` (FETCH_SIZE, then WRITE_SIZE, KB per
+    dispatch), each scaled by what the counter reads for the probe's plain
+    elementwise kernel of known size; written with the workload key and the
+    kernel sources' hash."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = re.sub(r"\(.*", "", r["Kernel_Name"])
+            a = acc.setdefault(name, {})
+            a[r["Dispatch_Id"]] = a.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    # the calibration kernel: the torch elementwise kernel that moves the most bytes
+    calib = sorted((k for k in fetch if "elementwise" in k.lower()), key=lambda k: -fetch[k])
+    if not calib:
+        raise SystemExit("no elementwise calibration kernel in the counter file")
+    f_scale = COPY_BYTES / (fetch[calib[0]] * 1024.0)
+    w_scale = COPY_BYTES / (write[calib[0]] * 1024.0)
+    ranks = sorted(k for k in fetch if re.search(r"k_ace_rank<", k))
+    fb = sum(fetch[k] for k in ranks) * 1024.0 * f_scale
+    wb = sum(write.get(k, 0.0) for k in ranks) * 1024.0 * w_scale
+    with open(key_json) as f:
+        key = json.load(f)
+    rec = {"kernel": "k_ace_rank<L>, one launch per coupled rank, one pass",
+           "kernels": ranks, "key": key, "kernel_sources": TRAFFIC_SOURCES,
+           "sources_sha256": sources_sha256(TRAFFIC_SOURCES),
+           "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb,
+           "calibration": {"fetch_scale": f_scale, "write_scale": w_scale, "kernel": calib[0],
+                           "reference_bytes_each_way": COPY_BYTES,
+                           "fetch_kb": fetch[calib[0]], "write_kb": write[calib[0]]}}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def recorded_traffic(prec, ap, key):
     """HBM bytes of one pass of the rank kernels from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy-type kernel),
     or None when the kernel sources or the workload differ from those the
     counters were taken on."""
-    import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     rec = os.path.join(here, "profiles", "ace_rank_traffic.json")
     if prec == ap.AP_PREC_FP64 or not os.path.exists(rec):
@@ -251,11 +313,7 @@ def recorded_traffic(prec, ap, key):
         d = json.load(f)
     if "kernel_sources" not in d or "sources_sha256" not in d or d.get("key") != key:
         return None
-    h = hashlib.sha256()
-    for src in d["kernel_sources"]:
-        with open(os.path.join(here, src), "rb") as f:
-            h.update(f.read())
-    return d["traffic_bytes"] if h.hexdigest() == d["sources_sha256"] else None
+    return d["traffic_bytes"] if sources_sha256(d["kernel_sources"]) == d["sources_sha256"] else None
 
 
 def describe(wl, mode, n_ace):
@@ -270,6 +328,9 @@ def describe(wl, mode, n_ace):
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -301,6 +362,9 @@ def main():
         for _ in range(3):
             ctx.step(st.sys, st, 0)
         torch.cuda.synchronize()
+        if args.probe_key:
+            with open(args.probe_key, "w") as f:
+                json.dump({"workload": wl.name, "mode": args.mode, "n_ace": int(st.n_ace.item())}, f)
         return
 
     t_setup = time.perf_counter()

@@ -68,6 +68,18 @@ __device__ __forceinline__ MixL load_level(const MixL* p) {
   return P;
 }
 
+// The same fields from the copy the fused kernel stages in LDS (kLevelInts
+// int32 per rank): LDS reads are not hoisted across the tile loop's LDS
+// stores, so the parameters of all ranks are never held in registers at once.
+__device__ __forceinline__ MixL load_level_lds(const int32_t* q) {
+  MixL P;
+  P.nrow = uni(q[0]); P.nrow16 = uni(q[1]); P.nch = uni(q[2]); P.arow = uni(q[3]);
+  P.rt = uni(q[4]); P.ct = uni(q[5]); P.kt = uni(q[6]); P.kstr = uni(q[7]); P.zstr = uni(q[8]);
+  P.grp0 = uni(q[9]); P.ngrp = uni(q[10]); P.bt0 = uni(q[11]); P.xonce = uni(q[12]);
+  P.zoff = uni(q[13]); P.rs0 = uni(q[14]);
+  return P;
+}
+
 __device__ __forceinline__ CgEnt load_ent(const CgEnt* p) {
   const int2 raw = *reinterpret_cast<const int2*>(p);
   const int w0 = uni(raw.x);
@@ -177,15 +189,17 @@ __device__ __forceinline__ void gemm_tiles(const MixDev& m, const MixL& P, const
 
 // Write the accumulators of coefficient set p (rows [p*nrow16, (p+1)*nrow16))
 // as FP32 Z[row][col] into LDS, undoing the row scale of the coefficients
-// and the column (atom) scale of X_L; both are powers of two, so this is exact.
+// (staged in LDS with the rank's tables, so that no per-lane load of them can
+// be hoisted out of the tile loop and held in registers) and the column
+// (atom) scale of X_L; both are powers of two, so this is exact.
 template <int RTW, int CTN>
-__device__ __forceinline__ void store_z(const MixDev& m, const MixL& P, const f32x4 (&acc)[RTW][CTN],
-                                        float* Z, const float* bn2, int L, int p, int wave,
+__device__ __forceinline__ void store_z(const MixL& P, const f32x4 (&acc)[RTW][CTN], float* Z,
+                                        const float* bn2, const float* rs_lds, int L, int p, int wave,
                                         int lane, int ncols) {
   const int col_l = lane & 15;
   const int r_l = 4 * (lane >> 4);
   const int w = 2 * L + 1;
-  cptr<float> rs = as_const(m.rscale) + P.rs0 + p * P.nrow16;
+  const float* rs = rs_lds + p * P.nrow16;
   int cex[CTN];
 #pragma unroll
   for (int c = 0; c < CTN; ++c) {
@@ -303,24 +317,10 @@ __device__ __forceinline__ void xb_entry(const float* Aa, const float* Ab, float
     if constexpr (c != 0.0f) X[q] = fmaf(c * Aa[i1], Ab[i2], X[q]);
   }
 }
-template <int LT, int LP, int L, int I0, int I1, int E>
-__device__ __forceinline__ void ad_entry(const float* Ap, const float* Zv, float* ga) {
-  constexpr int q = E % (2 * L + 1), i2 = (E / (2 * L + 1)) % (2 * LP + 1),
-                i1 = E / ((2 * L + 1) * (2 * LP + 1));
-  if constexpr (i1 >= I0 && i1 < I1 && cg_rule(i1 - LT, i2 - LP, q - L)) {
-    constexpr float c = (float)ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L);
-    if constexpr (c != 0.0f) ga[i1 - I0] = fmaf(c * Ap[i2], Zv[q], ga[i1 - I0]);
-  }
-}
 template <int LA, int LB, int L, int... E>
 __device__ __forceinline__ void xb_all(std::integer_sequence<int, E...>, const float* Aa,
                                        const float* Ab, float* X) {
   (xb_entry<LA, LB, L, E>(Aa, Ab, X), ...);
-}
-template <int LT, int LP, int L, int I0, int I1, int... E>
-__device__ __forceinline__ void ad_all(std::integer_sequence<int, E...>, const float* Ap,
-                                       const float* Zv, float* ga) {
-  (ad_entry<LT, LP, L, I0, I1, E>(Ap, Zv, ga), ...);
 }
 
 // One group of X_L: lane = (member j = lane/8, atom t = lane%8), all members
@@ -352,12 +352,48 @@ __device__ __forceinline__ void xbuild_group(const float* At, int4 mem, _Float16
 // the target: lane = (target n = lane/8, atom t = lane%8), target index
 // a = (n, LT), partners (n', LP) for every n'.  Every coupled channel {a, p}
 // of this L is visited from both of its indices (the coupled value is
-// symmetric in them), so the lane owns its sums.
+// symmetric in them), so the lane owns its sums.  The partner sum is taken
+// first, W[m2][M] = sum_n' f A_(n',LP,m2) Z_({a,p},M), so the coupling
+// coefficients enter once per target instead of once per partner:
+// dphi/dA_(a,m1) += sum_(m2,M) C^{LT LP L}_{m1 m2 M} W[m2][M].
+template <int LT, int LP, int L, int I0, int I1, int E>
+__device__ __forceinline__ void adw_entry(const float* Wv, float* ga) {
+  constexpr int w = 2 * L + 1;
+  constexpr int q = E % w, i2 = (E / w) % (2 * LP + 1), i1 = E / (w * (2 * LP + 1));
+  if constexpr (i1 >= I0 && i1 < I1 && cg_rule(i1 - LT, i2 - LP, q - L)) {
+    constexpr float c = (float)ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L);
+    if constexpr (c != 0.0f) ga[i1 - I0] = fmaf(c, Wv[i2 * w + q], ga[i1 - I0]);
+  }
+}
+template <int LT, int LP, int L, int I0, int I1, int... E>
+__device__ __forceinline__ void adw_all(std::integer_sequence<int, E...>, const float* Wv, float* ga) {
+  (adw_entry<LT, LP, L, I0, I1, E>(Wv, ga), ...);
+}
+// (i2, q) is used by some component of [I0, I1)
+template <int LT, int LP, int L, int I0, int I1>
+__device__ constexpr bool adw_used(int i2, int q) {
+  for (int i1 = I0; i1 < I1; ++i1)
+    if (cg_rule(i1 - LT, i2 - LP, q - L) && ce_real_cg(LT, LP, L, i1 - LT, i2 - LP, q - L) != 0.0)
+      return true;
+  return false;
+}
+template <int LT, int LP, int L, int I0, int I1, int E>
+__device__ __forceinline__ void adw_acc(const float* Ap, const float* Zv, float* Wv) {
+  constexpr int w = 2 * L + 1;
+  constexpr int q = E % w, i2 = E / w;
+  if constexpr (adw_used<LT, LP, L, I0, I1>(i2, q)) Wv[E] = fmaf(Ap[i2], Zv[q], Wv[E]);
+}
+template <int LT, int LP, int L, int I0, int I1, int... E>
+__device__ __forceinline__ void adw_acc_all(std::integer_sequence<int, E...>, const float* Ap,
+                                            const float* Zv, float* Wv) {
+  (adw_acc<LT, LP, L, I0, I1, E>(Ap, Zv, Wv), ...);
+}
+
 template <int LT, int LP, int L, int I0, int I1>
 __device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P, const float* At,
                                                  const float* Z, const int32_t* rows_lds, int j,
                                                  int t, float* ga) {
-  constexpr int w = 2 * L + 1;
+  constexpr int w = 2 * L + 1, w2 = 2 * LP + 1;
   const int lp1 = m.l_max + 1;
   const int nidx = m.n_max * lp1;
   const bool act = j < m.n_max;
@@ -365,21 +401,24 @@ __device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P,
   // the channel row of the next partner is fetched one partner ahead
   const int32_t* rp = rows_lds + a * nidx + LP;
   int row_next = act ? rp[0] : -1;
+  float Wv[w2 * w];
+#pragma unroll
+  for (int e = 0; e < w2 * w; ++e) Wv[e] = 0.f;
 #pragma unroll 1
   for (int np = 0; np < m.n_max; ++np) {
     const int pidx = np * lp1 + LP;
     const int row = row_next;
     row_next = (act && np + 1 < m.n_max) ? rp[(np + 1) * lp1] : -1;
-    float Ap[2 * LP + 1], Zv[w];
-#pragma unroll
-    for (int q = 0; q <= 2 * LP; ++q) Ap[q] = At[np * m.nlm + LP * LP + q];
+    float Ap[w2], Zv[w];
     const float f = row < 0 ? 0.f : (pidx == a ? 2.f : 1.f);
+#pragma unroll
+    for (int q = 0; q < w2; ++q) Ap[q] = f * At[np * m.nlm + LP * LP + q];
     const int zb = (row < 0 ? 0 : row) * P.zstr + t * w;
 #pragma unroll
-    for (int q = 0; q < w; ++q) Zv[q] = f * Z[zb + q];
-    ad_all<LT, LP, L, I0, I1>(
-        std::make_integer_sequence<int, (2 * LT + 1) * (2 * LP + 1) * (2 * L + 1)>{}, Ap, Zv, ga);
+    for (int q = 0; q < w; ++q) Zv[q] = Z[zb + q];
+    adw_acc_all<LT, LP, L, I0, I1>(std::make_integer_sequence<int, w2 * w>{}, Ap, Zv, Wv);
   }
+  adw_all<LT, LP, L, I0, I1>(std::make_integer_sequence<int, (2 * LT + 1) * w2 * w>{}, Wv, ga);
 }
 
 template <int LT, int L, int I0, int I1, int LP>
@@ -502,7 +541,8 @@ template <int L, int RTW, int CTN, bool XO>
 __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
                                        float* om2, unsigned char* big, float* phi_lds,
                                        const float* bn2, const int32_t* rows_lds,
-                                       const int4* mem_lds, int wave, int lane, int tid) {
+                                       const int4* mem_lds, const float* rs_lds, int wave, int lane,
+                                       int tid) {
   const int w = 2 * L + 1;
   const int ncols = kMT * w;
   _Float16* xh = reinterpret_cast<_Float16*>(big);
@@ -553,12 +593,12 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
     build_x();
     __syncthreads();
     gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 0);
-    store_z<RTW, CTN>(m, P, acc, Z, bn2, L, 0, wave, lane, ncols);
+    store_z<RTW, CTN>(P, acc, Z, bn2, rs_lds, L, 0, wave, lane, ncols);
     __syncthreads();
     adjoint_set(Z, 0);
     gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, 1);
     __syncthreads();  // every wavefront is done with Z of set 0
-    store_z<RTW, CTN>(m, P, acc, Z, bn2, L, 1, wave, lane, ncols);
+    store_z<RTW, CTN>(P, acc, Z, bn2, rs_lds, L, 1, wave, lane, ncols);
     __syncthreads();
     adjoint_set(Z, 1);
     __syncthreads();
@@ -570,7 +610,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       // Z_L of coefficient set p
       gemm_tiles<RTW, CTN>(m, P, xh, xl, acc, wave, lane, p);
       __syncthreads();  // X is dead from here on
-      store_z<RTW, CTN>(m, P, acc, Z, bn2, L, p, wave, lane, ncols);
+      store_z<RTW, CTN>(P, acc, Z, bn2, rs_lds, L, p, wave, lane, ncols);
       __syncthreads();
       adjoint_set(Z, p);
       __syncthreads();
@@ -604,6 +644,8 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
   for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
+  float* rs_lds = reinterpret_cast<float*>(mem_lds + P.ngrp * 8);
+  for (int q = tid; q < 2 * P.nrow16; q += kMThreads) rs_lds[q] = m.rscale[P.rs0 + q];
   // A of a tile's atoms and the gradient and phi sums of the lower ranks are
   // loaded into registers ahead of the tile that uses them
   constexpr int kPf = (kMT * (8 * kMaxLM + 1) + kMThreads - 1) / kMThreads;
@@ -657,8 +699,8 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
     const int64_t base = (int64_t)tile * kMT * m.nA;
     const int next = tile + (int)gridDim.x;
     if (kEarly && next < n_tiles) fetch(next);
-    rank_L<L, RTW, CTN, XO>(m, P, A, om1, om2, big, phi_lds, bn_lds, rows_lds, mem_lds, wave, lane,
-                            tid);
+    rank_L<L, RTW, CTN, XO>(m, P, A, om1, om2, big, phi_lds, bn_lds, rows_lds, mem_lds, rs_lds, wave,
+                            lane, tid);
     __syncthreads();
     if (!kEarly && next < n_tiles) fetch(next);
     for (int q = tid; q < nt * m.nA; q += kMThreads) {

@@ -703,11 +703,20 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
         if (!(std::abs(lt - lp) <= L && L <= lt + lp && ((lt + lp + L) & 1) == 0)) continue;
         const auto& C = cgcache[std::make_tuple(lt, lp, L)];
         const int w2 = 2 * lp + 1;
-        int nnz = 0;
-        for (int p1 = i0; p1 < i1; ++p1)
-          for (int q = 0; q < w2; ++q)
-            for (int M = 0; M < w; ++M) nnz += C[((size_t)p1 * w2 + q) * w + M] != 0.0;
-        c += nmax * (2.0 * nnz + w + w2 + 8.0);
+        // the partner sum W[m2][M] over the entries some component uses,
+        // then one pass over the coupling coefficients
+        int nnz = 0, used = 0;
+        for (int q = 0; q < w2; ++q)
+          for (int M = 0; M < w; ++M) {
+            bool u = false;
+            for (int p1 = i0; p1 < i1; ++p1)
+              if (C[((size_t)p1 * w2 + q) * w + M] != 0.0) {
+                ++nnz;
+                u = true;
+              }
+            used += u;
+          }
+        c += nmax * (used + w + 2.0 * w2 + 8.0) + nnz;
       }
       if (lt == L) c += 3.0 * (i1 - i0) + 12.0;
       return c;
@@ -772,10 +781,14 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     }
     adj_ptr.push_back((int32_t)adj_units.size());
   }
-  // LDS head: A, omega of both sets, phi [8][2], per-atom norm bound [8]
-  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8) * 4 + 15) / 16 * 16);
+  // LDS head: A, omega of both sets, phi [8][2], per-atom norm bound [8], and
+  // the level parameters of every rank (fused kernel)
+  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8) * 4 + 15) / 16 * 16 +
+                        (size_t)(2 * kMaxL + 1) * kLevelInts * 4);
   size_t tab = (size_t)nidx * nidx * 4;
-  for (int L = 0; L <= Lmax; ++L) tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16);
+  // per rank: the channel rows, the coupling groups and the row scales of both sets
+  for (int L = 0; L <= Lmax; ++L)
+    tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16 + (size_t)x.lv[L].nrow16 * 2 * 4);
   x.big_off = (int32_t)((x.tab_off + tab + 15) / 16 * 16);
   // ranks whose X_L and Z_L fit in LDS together keep X_L for both sets
   for (int L = 0; L <= Lmax; ++L) {

@@ -111,6 +111,9 @@ struct CgEnt {
 // owns at most kMixRtw[L] 16-row tiles of one coefficient set of C_L
 // (row tile rt = wave + kMixWaves * i).
 constexpr int kMixWaves = 8;
+// int32 slots per rank of the level parameters the fused rank kernel stages in
+// LDS (the 15 fields of MixL, padded)
+constexpr int kLevelInts = 16;
 constexpr int kMixRtw[2 * kMaxL + 1] = {2, 3, 3, 3, 3, 2, 2, 1, 1};
 // launch modes of the rank phase: one kernel per coupled rank; all ranks in
 // one persistent launch with tiles round-robin; the same with tiles from a

@@ -16,22 +16,25 @@
 
 namespace ap {
 
-// coupled rank L of the current tile: its channel tables into LDS, then the
+// coupled rank L of the current tile: its channel tables and row scales into
+// LDS, then the
 // rank body (which ends with a workgroup barrier).  Whether rank L keeps X_L
 // for both coefficient sets (bit L of XOMASK) is fixed at compile time, so
 // only the variant the model's LDS layout chose is generated.
 template <int L, uint32_t XOMASK>
 __device__ __forceinline__ void fused_rank(const MixDev& m, float* A, float* om1, float* om2,
                                            unsigned char* big, float* phi_lds, const float* bn_lds,
-                                           int32_t* rows_lds, int4* mem_lds, int wave, int lane,
-                                           int tid) {
-  const MixL P = load_level(m.lv_d + L);
+                                           const int32_t* lv_lds, int32_t* rows_lds, int4* mem_lds,
+                                           int wave, int lane, int tid) {
+  const MixL P = load_level_lds(lv_lds + L * kLevelInts);
   const int nidx = m.n_max * (m.l_max + 1);
   for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
+  float* rs_lds = reinterpret_cast<float*>(mem_lds + P.ngrp * 8);
+  for (int q = tid; q < 2 * P.nrow16; q += kMThreads) rs_lds[q] = m.rscale[P.rs0 + q];
   __syncthreads();
   rank_L<L, kMixRtw[L], L + 1, ((XOMASK >> L) & 1u) != 0>(m, P, A, om1, om2, big, phi_lds, bn_lds,
-                                                          rows_lds, mem_lds, wave, lane, tid);
+                                                          rows_lds, mem_lds, rs_lds, wave, lane, tid);
 }
 
 // ranks L..LMAX of the tile in order; the next tile's A is loaded into
@@ -39,13 +42,14 @@ __device__ __forceinline__ void fused_rank(const MixDev& m, float* A, float* om1
 template <int L, int LMAX, uint32_t XOMASK, typename Fetch>
 __device__ __forceinline__ void fused_ranks(const MixDev& m, float* A, float* om1, float* om2,
                                             unsigned char* big, float* phi_lds, const float* bn_lds,
-                                            int32_t* rows_lds, int4* mem_lds, int wave, int lane,
-                                            int tid, Fetch&& fetch_next) {
+                                            const int32_t* lv_lds, int32_t* rows_lds, int4* mem_lds,
+                                            int wave, int lane, int tid, Fetch&& fetch_next) {
   if constexpr (L <= LMAX) {
     if constexpr (L == (LMAX > 0 ? LMAX - 1 : 0)) fetch_next();
-    fused_rank<L, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, rows_lds, mem_lds, wave, lane, tid);
-    fused_ranks<L + 1, LMAX, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, rows_lds, mem_lds, wave,
-                                     lane, tid, fetch_next);
+    fused_rank<L, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, lv_lds, rows_lds, mem_lds, wave, lane,
+                          tid);
+    fused_ranks<L + 1, LMAX, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, lv_lds, rows_lds, mem_lds,
+                                     wave, lane, tid, fetch_next);
   }
 }
 
@@ -65,8 +69,13 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank_fused(
   const int nidx = m.n_max * (m.l_max + 1);
   int32_t* rows_lds = reinterpret_cast<int32_t*>(lds + m.tab_off);
   int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
+  int32_t* lv_lds = reinterpret_cast<int32_t*>(lds + m.tab_off) - (2 * kMaxL + 1) * kLevelInts;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int q = tid; q < (LMAX + 1) * kLevelInts; q += kMThreads) {
+    const int L = q / kLevelInts, f = q % kLevelInts;
+    lv_lds[q] = f < 15 ? reinterpret_cast<const int32_t*>(m.lv_d + L)[f] : 0;
+  }
   const int n_items = n_ace_p ? *n_ace_p : n_all;
   const int n_tiles = (n_items + kMT - 1) / kMT;
   constexpr int kPf = (kMT * (8 * kMaxLM + 1) + kMThreads - 1) / kMThreads;
@@ -119,8 +128,8 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank_fused(
     const int nt = min(kMT, n_items - tile * kMT);
     const int64_t base = (int64_t)tile * kMT * m.nA;
     const int next = take(tile + (int)gridDim.x);
-    fused_ranks<0, LMAX, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, rows_lds, mem_lds, wave, lane,
-                                 tid, [&]() {
+    fused_ranks<0, LMAX, XOMASK>(m, A, om1, om2, big, phi_lds, bn_lds, lv_lds, rows_lds, mem_lds, wave,
+                                 lane, tid, [&]() {
                                    if (next < n_tiles) fetch(next);
                                  });
     for (int q = tid; q < nt * m.nA; q += kMThreads) {
