@@ -793,9 +793,18 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   // ranks whose X_L and Z_L fit in LDS together keep X_L for both sets
   for (int L = 0; L <= Lmax; ++L) {
     MixL& P = x.lv[L];
-    P.xonce = (size_t)x.big_off + xbytes[L] + zbytes[L] + 1024 <= 160 * 1024 ? 1 : 0;
+    // Z_L's row stride: 8w + 4 floats puts the rows r and r + 4 that one store
+    // instruction writes (the MFMA result layout) 16 banks apart; 8w + 1 only
+    // where that is what lets X_L and Z_L fit together
+    const int w = 2 * L + 1;
+    auto fits = [&](int zstr) {
+      return (size_t)x.big_off + xbytes[L] + (size_t)P.nrow * zstr * 4 + 1024 <= 160 * 1024;
+    };
+    P.zstr = fits(8 * w + 4) || !fits(8 * w + 1) ? 8 * w + 4 : 8 * w + 1;
+    zbytes[L] = (size_t)P.nrow * P.zstr * 4;
+    P.xonce = fits(P.zstr) ? 1 : 0;
     P.zoff = P.xonce ? (int32_t)xbytes[L] : 0;
-    if (P.xonce) big = std::max(big, xbytes[L] + zbytes[L]);
+    big = std::max(big, P.xonce ? xbytes[L] + zbytes[L] : zbytes[L]);
   }
   x.big_bytes = (int32_t)big;
   if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)

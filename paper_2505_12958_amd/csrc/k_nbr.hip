@@ -249,12 +249,14 @@ hipError_t launch_fill_nbr(const SysView& sv, const double* pos, const int32_t* 
 
 // --------------------------------------------------------------------------
 // One workgroup per cell.  The candidates of the cell's stencil (at most 27
-// deduplicated cells) are gathered into LDS once and shared by the cell's
-// atoms, one wavefront per atom: lanes test 64 candidates at a time with the
-// canonical FP64 rule, accepted indices are compacted into a per-wavefront
-// LDS list with a ballot, then each lane ranks its entries (indices are
-// unique) and stores them in ascending order.  A cell whose stencil holds
-// more than kMaxCand candidates falls back to the kernel above for its atoms.
+// deduplicated cells) are gathered into LDS once (as FP32 coordinates) and
+// shared by the cell's atoms, one wavefront per atom: lanes screen 64
+// candidates at a time in FP32 with a 0.05 A margin and compact the
+// survivors (about a quarter); the survivors are tested with the canonical
+// FP64 rule, accepted indices are compacted into a per-wavefront LDS list
+// with a ballot, then each lane ranks its entries (indices are unique) and
+// stores them in ascending order.  A cell whose stencil holds more than
+// kMaxCand candidates falls back to the kernel above for its atoms.
 constexpr int kCellThreads = 256;
 constexpr int kCellWaves = kCellThreads / 64;
 constexpr int kMaxCand = 512;
@@ -263,7 +265,10 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
     SysView sv, const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
     const double4* __restrict__ cell_pos, int32_t* __restrict__ nbr, int32_t* __restrict__ count,
     int cap, int32_t* __restrict__ overflow, int32_t* __restrict__ big_atoms) {
-  __shared__ double4 cpos[kMaxCand];
+  // candidates as float (x, y, z) plus their cell-order index: the screen;
+  // the exact FP64 test reads the survivors' positions from cell_pos
+  __shared__ float4 cposf[kMaxCand];
+  __shared__ int cand[kCellWaves][kMaxCand];
   __shared__ __align__(16) int list[kCellWaves][kListLds + 4];
   __shared__ int st_src[32];   // first cell-ordered atom of each stencil cell
   __shared__ int st_pre[33];   // exclusive prefix of the stencil cells' counts
@@ -340,23 +345,58 @@ __global__ __launch_bounds__(kCellThreads) void k_fill_nbr_cell(
       const int mid = (lo + hi + 1) >> 1;
       if (st_pre[mid] <= q) lo = mid; else hi = mid - 1;
     }
-    cpos[q] = cell_pos[st_src[lo] + (q - st_pre[lo])];
+    const int src = st_src[lo] + (q - st_pre[lo]);
+    const double4 p = cell_pos[src];
+    cposf[q] = make_float4((float)p.x, (float)p.y, (float)p.z, __int_as_float(src));
   }
   __syncthreads();
   const bool ortho = sv.ortho[s] != 0;
   const double* H = sv.H + 9 * s;
   const double* Hi = sv.Hi + 9 * s;
+  // screen in FP32 on orthorhombic boxes: the minimum-image distance of the
+  // rounded positions is within 0.02 A of the exact one for coordinates below
+  // 1e5 A, so every pair with r < r_c passes r < r_c + 0.05 A; the exact
+  // canonical FP64 test then decides (triclinic boxes: every candidate goes on)
+  const float Lf[3] = {(float)H[0], (float)H[4], (float)H[8]};
+  const float iLf[3] = {1.f / Lf[0], 1.f / Lf[1], 1.f / Lf[2]};
+  const float rs = (float)sqrt(sv.rc2) + 0.05f;
+  const float rs2 = rs * rs;
   int* lw = list[wave];
+  int* cw = cand[wave];
   for (int a = wave; a < n_here; a += kCellWaves) {
     const double4 pi = cell_pos[first + a];
     const int i = (int)pi.w;
-    int cnt = 0;
+    const float xf = (float)pi.x, yf = (float)pi.y, zf = (float)pi.z;
+    int npass = 0;
     for (int base = 0; base < total; base += 64) {
+      const int q = base + lane;
+      bool pass = false;
+      int src = 0;
+      if (q < total) {
+        const float4 pf = cposf[q];
+        src = __float_as_int(pf.w);
+        if (ortho) {
+          float d[3] = {pf.x - xf, pf.y - yf, pf.z - zf};
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if (sv.per[k]) d[k] -= Lf[k] * rintf(d[k] * iLf[k]);
+          pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rs2;
+        } else {
+          pass = true;
+        }
+      }
+      const unsigned long long b = __ballot(pass);
+      if (pass) cw[npass + __popcll(b & ((1ull << lane) - 1ull))] = src;
+      npass += __popcll(b);
+    }
+    __syncwarp_ap();
+    int cnt = 0;
+    for (int base = 0; base < npass; base += 64) {
       const int q = base + lane;
       bool acc = false;
       int j = -1;
-      if (q < total) {
-        const double4 pj = cpos[q];
+      if (q < npass) {
+        const double4 pj = cell_pos[cw[q]];
         j = (int)pj.w;
         if (j != i) {
           double dx, dy, dz;
