@@ -43,15 +43,12 @@
  * ap_step with check_every > 0).  An asynchronous HIP fault surfaces as
  * AP_ERR_HIP from the next call that synchronises.
  *
- * Determinism: the FP64 path has no floating-point atomics; forces are
- * gathered with a reverse-slot index and every sum has a fixed order, so its
- * results are bitwise reproducible run to run.  The mixed path adds the
- * partial sums of each atom's phi_p (a handful per atom) with FP32 atomic
- * adds in LDS, so its energies and forces may differ in the last FP32 bits
- * between runs (far inside its 1e-5 tolerance); everything else there has a
- * fixed order.  Integer atomics (work queues, cell counts, overflow maxima,
- * the switching spread's maximum over FP64 bit patterns of non-negative
- * values) do not affect results.
+ * Determinism: no floating-point atomics in either precision; forces are
+ * gathered with a reverse-slot index and every sum has a fixed order (the
+ * mixed path's partial phi sums of a rank are added slot by slot), so results
+ * are bitwise reproducible run to run.  Integer atomics (work queues, cell
+ * counts, overflow maxima, the switching spread's maximum over FP64 bit
+ * patterns of non-negative values) do not affect results.
  */
 #ifndef AP_H
 #define AP_H

@@ -437,7 +437,8 @@ __device__ __forceinline__ void adjoint_lp(const MixDev& m, const MixL& P, const
 // target (n, LT), summed over all partner patterns; jobs write disjoint
 // gradient entries, so the sums are stored without atomics.  The job with
 // LT = L also takes the A rows of X_L: dphi/dA_{n,L,M} gets Z of row (n, L)
-// and phi gets A.Z (summed over n for each atom).
+// and its part K of A.Z (summed over n for each atom) goes to slot K of the
+// atom's partial phi sums, which the rank adds up in a fixed order.
 template <int LT, int L, int NP, int K>
 __device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, const float* At,
                                             const float* Z, float* omt, float* phi_t,
@@ -463,7 +464,7 @@ __device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, cons
       sa += __shfl_xor(sa, 8);
       sa += __shfl_xor(sa, 16);
       sa += __shfl_xor(sa, 32);
-      if (j == 0) atomicAdd(phi_t, sa);
+      if (j == 0) phi_t[K * kMT] = sa;
     }
   }
   if (act) {
@@ -489,7 +490,7 @@ __device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, cons
   X(2, 0) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) \
   X(4, 0) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
 
-// Build the channel rows of X_L (bf16 hi/lo) for the 8 atoms of the tile.
+// Build the channel rows of X_L (fp16 hi/lo) for the 8 atoms of the tile.
 // Group g of this L: members {row, A offset of a, A offset of b, la*5+lb}.
 template <int L>
 __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const float* A, _Float16* xh,
@@ -512,13 +513,14 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
 
 // Gradient of phi_p with respect to A from the coupled channels of X_L.  The
 // wavefront's jobs (target l, component part) come from a schedule the
-// library balanced over the workgroup's wavefronts.
+// library balanced over the workgroup's wavefronts.  part_p: the set's
+// partial phi sums, [4 slots][8 atoms].
 template <int L>
 __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
-                                        const float* Z, float* om, float* phi_p,
+                                        const float* Z, float* om, float* part_p,
                                         const int32_t* rows_lds, int wave, int lane) {
   const int j = lane >> 3, t = lane & 7;
-  float* phi_t = phi_p + 2 * t;
+  float* phi_t = part_p + t;
   const float* At = A + t * m.apad;
   cptr<int32_t> ptr = as_const(m.adj_ptr) + L * (kMWaves + 1);
   const int u0 = uni(ptr[wave]), u1 = uni(ptr[wave + 1]);
@@ -580,10 +582,22 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       xl[tid * P.kstr + P.nch + m.n_max] = (_Float16)0.0f;
     }
   };
+  // partial phi sums of this rank, [set][slot][atom]: slots 0-2 the parts of
+  // the A-row job, slot 3 the constant row (L = 0); every slot is written by
+  // one lane and the slots are added to the atom's phi in a fixed order once
+  // the rank is done, so the mixed path's sums do not depend on timing
+  float* part = phi_lds + 3 * kMT;
+  if (tid < 8 * kMT) part[tid] = 0.f;
   auto adjoint_set = [&](const float* Z, int p) {
     float* om = p == 0 ? om1 : om2;
-    adjoint<L>(m, P, A, Z, om, phi_lds + p, rows_lds, wave, lane);
-    if (L == 0 && tid < kMT) atomicAdd(&phi_lds[tid * 2 + p], 2.f * Z[(P.nch + m.n_max) * P.zstr + tid]);
+    adjoint<L>(m, P, A, Z, om, part + p * 4 * kMT, rows_lds, wave, lane);
+    if (L == 0 && tid < kMT) part[(p * 4 + 3) * kMT + tid] = 2.f * Z[(P.nch + m.n_max) * P.zstr + tid];
+  };
+  auto add_parts = [&]() {
+    if (tid < 2 * kMT) {
+      const float* q = part + (tid & 1) * 4 * kMT + (tid >> 1);
+      phi_lds[tid] += ((q[0] + q[kMT]) + q[2 * kMT]) + q[3 * kMT];
+    }
   };
   f32x4 acc[RTW][CTN];
   if constexpr (XO) {
@@ -602,6 +616,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
     __syncthreads();
     adjoint_set(Z, 1);
     __syncthreads();
+    add_parts();
   } else {
     float* Z = reinterpret_cast<float*>(big);
     for (int p = 0; p < 2; ++p) {
@@ -615,6 +630,7 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       adjoint_set(Z, p);
       __syncthreads();
     }
+    add_parts();
   }
 }
 
@@ -630,7 +646,7 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   float* A = reinterpret_cast<float*>(lds);
   float* om1 = A + kMT * m.apad;
   float* om2 = om1 + kMT * m.apad;
-  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2]
+  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2], then [2][4][kMT] partial sums
   float* bn_lds = phi_lds + 2 * kMT;                    // [kMT]
   unsigned char* big = lds + m.big_off;
   const int tid = threadIdx.x, lane = tid & 63;

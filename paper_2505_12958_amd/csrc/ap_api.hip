@@ -675,8 +675,7 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
       const int pid = pat_id[key];
       const auto& mem = kv.second;
       // members of a group are taken with stride n_groups from the (a, b)
-      // ordered list, so they rarely share a single index (fewer colliding
-      // atomic adds in the adjoint)
+      // ordered list, so they rarely share a single index
       const size_t ng = (mem.size() + 7) / 8;
       for (size_t g = 0; g < ng; ++g) {
         grp_pat.push_back(pid);
@@ -781,9 +780,10 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     }
     adj_ptr.push_back((int32_t)adj_units.size());
   }
-  // LDS head: A, omega of both sets, phi [8][2], per-atom norm bound [8], and
-  // the level parameters of every rank (fused kernel)
-  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8) * 4 + 15) / 16 * 16 +
+  // LDS head: A, omega of both sets, phi [8][2], per-atom norm bound [8], the
+  // rank's partial phi sums [2][4][8], and the level parameters of every rank
+  // (fused kernel)
+  x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8 + 64) * 4 + 15) / 16 * 16 +
                         (size_t)(2 * kMaxL + 1) * kLevelInts * 4);
   size_t tab = (size_t)nidx * nidx * 4;
   // per rank: the channel rows, the coupling groups and the row scales of both sets

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank_fused(
   float* A = reinterpret_cast<float*>(lds);
   float* om1 = A + kMT * m.apad;
   float* om2 = om1 + kMT * m.apad;
-  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2]
+  float* phi_lds = om2 + kMT * m.apad;                  // [kMT][2], then [2][4][kMT] partial sums
   float* bn_lds = phi_lds + 2 * kMT;                    // [kMT]
   unsigned char* big = lds + m.big_off;
   const int nidx = m.n_max * (m.l_max + 1);

@@ -122,6 +122,19 @@ def test_fp64_bitwise_reproducible():
     assert np.array_equal(a["virial"], b["virial"])
 
 
+@pytest.mark.parametrize("name", ["wslab10", "bulk2000"])
+def test_mixed_bitwise_reproducible(name):
+    """The mixed path has no floating-point atomics either (the partial phi
+    sums of a rank are added in a fixed order), so two runs agree bit for bit."""
+    from paper_2505_12958_amd import ap
+    wl, _ = oracle(name)
+    a = run_force(wl, precision=ap.AP_PREC_MIXED)
+    b = run_force(wl, precision=ap.AP_PREC_MIXED)
+    assert np.array_equal(a["forces"], b["forces"])
+    assert np.array_equal(a["e_atom"], b["e_atom"])
+    assert np.array_equal(a["virial"], b["virial"])
+
+
 def test_sum_of_forces_zero():
     wl, _ = oracle("batch6")
     g = run_force(wl)
