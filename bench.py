@@ -101,7 +101,7 @@ def timed_steps(torch, ap, ctx, wl, steps, warmup, profile):
 
 # ---------------------------------------------------------------- CPU baseline
 def host_cores():
-    """Cores this process may use, capped at the GPU machine's CPU share per GPU."""
+    """Cores this process may use, capped at 16 (the host CPU share of one GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
