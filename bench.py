@@ -17,7 +17,9 @@ with the phase timers on gives the per-phase times and the duration of the
 rank kernels (HIP events on the launch stream) for the roofline.  The
 relative force error of the timed precision against the FP64 path is
 measured on the same positions before timing; the FP64 path is timed too
-(--fp64-steps 0 skips that timing).
+(--fp64-steps 0 skips that timing).  A secondary number, `force_eval`, is the
+median of 100 single force evaluations (no integration) timed with HIP events
+after 10 warm-ups.
 
 Roofline (algorithmic counts of the model, per phase):
   T_roof = sum over phases of max(bytes / 8 TB/s, VALU flops / 157.3 TFLOP/s
@@ -51,6 +53,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     p.add_argument("--fp64-steps", type=int, default=5)
+    p.add_argument("--force-evals", type=int, default=100,
+                   help="single force evaluations timed for the secondary number (0 skips)")
     p.add_argument("--workload", type=int, default=3)
     p.add_argument("--mode", choices=["ap", "ace", "eam"], default="ap",
                    help="ap: the workload's switching rule; ace / eam: lambda = 1 / 0 everywhere")
@@ -97,6 +101,28 @@ def timed_steps(torch, ap, ctx, wl, steps, warmup, profile):
         ctx.profile(False)
     ctx.check()
     return st, t1 - t0, prof
+
+
+def force_evals(torch, ap, ctx, wl, n, warmup=10):
+    """Median duration of n single force evaluations (ap_step with 0 steps),
+    each bracketed by HIP events on the stream the library is called on."""
+    if n <= 0:
+        return None
+    st = ap.MD(wl)
+    for _ in range(warmup):
+        ctx.step(st.sys, st, 0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        ctx.step(st.sys, st, 0)
+        b.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    med = ms[n // 2] if n % 2 else 0.5 * (ms[n // 2 - 1] + ms[n // 2])
+    return {"evaluations": n, "median_ms": med, "min_ms": ms[0], "max_ms": ms[-1],
+            "atom_evals_per_s": wl.n_atoms / (med * 1e-3)}
 
 
 # ---------------------------------------------------------------- CPU baseline
@@ -399,6 +425,9 @@ def main():
     # headline: phase timers off
     _, dt, _ = timed_steps(torch, ap, ctx, wl, args.steps, args.warmup, profile=False)
     value = N * args.steps / dt
+    # secondary: single force evaluations (blend, neighbours, EAM, ACE, indenter;
+    # no integration), median over HIP-event-timed calls after warm-ups
+    fe = force_evals(torch, ap, ctx, wl, args.force_evals)
     # phases and the rank kernels' duration: a separate pass with the timers on
     _, dt_prof, prof = timed_steps(torch, ap, ctx, wl, max(3, args.steps // 2), 1, profile=True)
     steps_prof = max(3, args.steps // 2)
@@ -456,6 +485,7 @@ def main():
         "virial_rel_err_vs_fp64": err_w, "fp64_path_value": v64,
         "vs_fp64_path": value / v64 if v64 else None,
         "phase_ms_per_step": phases, "ms_per_step_profiled": dt_prof / steps_prof * 1e3,
+        "force_eval": fe,
         "roofline": roof,
     }
     if pool is not None:
