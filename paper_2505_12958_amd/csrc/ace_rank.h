@@ -391,7 +391,7 @@ __device__ __forceinline__ void adw_acc_all(std::integer_sequence<int, E...>, co
 
 template <int LT, int LP, int L, int I0, int I1>
 __device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P, const float* At,
-                                                 const float* Z, const int32_t* rows_lds, int j,
+                                                 const float* Z, const int16_t* rows_lds, int j,
                                                  int t, float* ga) {
   constexpr int w = 2 * L + 1, w2 = 2 * LP + 1;
   const int lp1 = m.l_max + 1;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P,
   const bool act = j < m.n_max;
   const int a = j * lp1 + LT;
   // the channel row of the next partner is fetched one partner ahead
-  const int32_t* rp = rows_lds + a * nidx + LP;
+  const int16_t* rp = rows_lds + a * nidx + LP;
   int row_next = act ? rp[0] : -1;
   float Wv[w2 * w];
 #pragma unroll
@@ -423,7 +423,7 @@ __device__ __forceinline__ void adjoint_partners(const MixDev& m, const MixL& P,
 
 template <int LT, int L, int I0, int I1, int LP>
 __device__ __forceinline__ void adjoint_lp(const MixDev& m, const MixL& P, const float* At,
-                                           const float* Z, const int32_t* rows_lds, int j, int t,
+                                           const float* Z, const int16_t* rows_lds, int j, int t,
                                            float* ga) {
   if constexpr (LP <= kMaxL) {
     if constexpr (iabs_c(LT - LP) <= L && L <= LT + LP && ((LT + LP + L) & 1) == 0) {
@@ -442,7 +442,7 @@ __device__ __forceinline__ void adjoint_lp(const MixDev& m, const MixL& P, const
 template <int LT, int L, int NP, int K>
 __device__ __forceinline__ void adjoint_job(const MixDev& m, const MixL& P, const float* At,
                                             const float* Z, float* omt, float* phi_t,
-                                            const int32_t* rows_lds, int j, int t) {
+                                            const int16_t* rows_lds, int j, int t) {
   constexpr int w = 2 * L + 1;
   constexpr int I0 = K * (2 * LT + 1) / NP, I1 = (K + 1) * (2 * LT + 1) / NP;
   const bool act = j < m.n_max;
@@ -518,7 +518,7 @@ __device__ __forceinline__ void xbuild(const MixDev& m, const MixL& P, const flo
 template <int L>
 __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const float* A,
                                         const float* Z, float* om, float* part_p,
-                                        const int32_t* rows_lds, int wave, int lane) {
+                                        const int16_t* rows_lds, int wave, int lane) {
   const int j = lane >> 3, t = lane & 7;
   float* phi_t = part_p + t;
   const float* At = A + t * m.apad;
@@ -542,15 +542,20 @@ __device__ __forceinline__ void adjoint(const MixDev& m, const MixL& P, const fl
 template <int L, int RTW, int CTN, bool XO>
 __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A, float* om1,
                                        float* om2, unsigned char* big, float* phi_lds,
-                                       const float* bn2, const int32_t* rows_lds,
+                                       const float* bn2, const int16_t* rows_lds,
                                        const int4* mem_lds, const float* rs_lds, int wave, int lane,
                                        int tid) {
   const int w = 2 * L + 1;
   const int ncols = kMT * w;
+  // X_L column-major (k contiguous), hi then lo.  Where Z_L shares the LDS
+  // region (XO), only the tile's ncols columns are stored: the contraction's
+  // reads of the padding columns of the last column tile then fall on lo
+  // (or, for lo, on Z) and feed only result columns that are never stored.
+  const int xcols = XO ? ncols : P.ct * 16;
   _Float16* xh = reinterpret_cast<_Float16*>(big);
-  _Float16* xl = xh + (size_t)P.ct * 16 * P.kstr;
-  // coupled operand X_L: zero padding (rows past nrow up to the k tiles,
-  // columns past the tile's atoms), channel rows, A rows, constant row
+  _Float16* xl = xh + (size_t)xcols * P.kstr;
+  // coupled operand X_L: zero padding (rows past nrow up to the k tiles, and
+  // the padding columns where they are stored), channel rows, A rows, constant row
   auto build_x = [&]() {
     const int kpad = P.kt * 32;
     const int padr = kpad - P.nrow;
@@ -559,11 +564,13 @@ __device__ __forceinline__ void rank_L(const MixDev& m, const MixL& P, float* A,
       xh[o] = (_Float16)0.0f;
       xl[o] = (_Float16)0.0f;
     }
-    const int padc = P.ct * 16 - ncols;
-    for (int q = tid; q < padc * kpad; q += kMThreads) {
-      const int o = (ncols + q / kpad) * P.kstr + q % kpad;
-      xh[o] = (_Float16)0.0f;
-      xl[o] = (_Float16)0.0f;
+    if constexpr (!XO) {
+      const int padc = P.ct * 16 - ncols;
+      for (int q = tid; q < padc * kpad; q += kMThreads) {
+        const int o = (ncols + q / kpad) * P.kstr + q % kpad;
+        xh[o] = (_Float16)0.0f;
+        xl[o] = (_Float16)0.0f;
+      }
     }
     xbuild<L>(m, P, A, xh, xl, mem_lds, bn2, wave, lane);
     if (P.arow) {
@@ -656,9 +663,10 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank(
   const MixL P = load_level(m.lv_d + L);
   // stage this rank's channel tables in LDS (read by every tile)
   const int nidx = m.n_max * (m.l_max + 1);
-  int32_t* rows_lds = reinterpret_cast<int32_t*>(lds + m.tab_off);
-  int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
-  for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
+  int16_t* rows_lds = reinterpret_cast<int16_t*>(lds + m.tab_off);
+  int4* mem_lds = reinterpret_cast<int4*>(lds + m.tab_off + (nidx * nidx * 2 + 15) / 16 * 16);
+  for (int q = tid; q < nidx * nidx; q += kMThreads)
+    rows_lds[q] = (int16_t)m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
   float* rs_lds = reinterpret_cast<float*>(mem_lds + P.ngrp * 8);
   for (int q = tid; q < 2 * P.nrow16; q += kMThreads) rs_lds[q] = m.rscale[P.rs0 + q];

@@ -785,11 +785,17 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
   // (fused kernel)
   x.tab_off = (int32_t)(((size_t)(3 * 8 * x.apad + 16 + 8 + 64) * 4 + 15) / 16 * 16 +
                         (size_t)(2 * kMaxL + 1) * kLevelInts * 4);
-  size_t tab = (size_t)nidx * nidx * 4;
+  // the channel row table is staged as int16 (rows < 2^15)
+  for (int L = 0; L <= Lmax; ++L)
+    if (x.lv[L].nrow >= 32768) return fail(ctx, AP_ERR_UNSUPPORTED, "too many coupled rows for one rank");
+  const size_t rows_bytes = ((size_t)nidx * nidx * 2 + 15) / 16 * 16;
+  size_t tab = rows_bytes;
   // per rank: the channel rows, the coupling groups and the row scales of both sets
   for (int L = 0; L <= Lmax; ++L)
-    tab = std::max(tab, (size_t)nidx * nidx * 4 + (size_t)x.lv[L].ngrp * 8 * 16 + (size_t)x.lv[L].nrow16 * 2 * 4);
+    tab = std::max(tab, rows_bytes + (size_t)x.lv[L].ngrp * 8 * 16 + (size_t)x.lv[L].nrow16 * 2 * 4);
   x.big_off = (int32_t)((x.tab_off + tab + 15) / 16 * 16);
+  // room the kernels' own static LDS needs beside the dynamic allocation
+  constexpr size_t kLdsReserve = 256;
   // ranks whose X_L and Z_L fit in LDS together keep X_L for both sets
   for (int L = 0; L <= Lmax; ++L) {
     MixL& P = x.lv[L];
@@ -797,17 +803,23 @@ static ap_status fold_ace(Ctx* ctx, const ap_ace_model* m) {
     // instruction writes (the MFMA result layout) 16 banks apart; 8w + 1 only
     // where that is what lets X_L and Z_L fit together
     const int w = 2 * L + 1;
+    // beside Z_L, X_L holds only the tile's 8w columns (hi, then lo); the
+    // contraction's reads of the last column tile's padding run on into the
+    // next region, which must cover them
+    const size_t x_tight = ((size_t)8 * w * P.kstr * 2 * 2 + 15) / 16 * 16;
+    const size_t overread = (size_t)(P.ct * 16 - 8 * w) * P.kstr * 2;
     auto fits = [&](int zstr) {
-      return (size_t)x.big_off + xbytes[L] + (size_t)P.nrow * zstr * 4 + 1024 <= 160 * 1024;
+      const size_t zb = (size_t)P.nrow * zstr * 4;
+      return zb >= overread && (size_t)x.big_off + x_tight + zb + kLdsReserve <= 160 * 1024;
     };
     P.zstr = fits(8 * w + 4) || !fits(8 * w + 1) ? 8 * w + 4 : 8 * w + 1;
     zbytes[L] = (size_t)P.nrow * P.zstr * 4;
     P.xonce = fits(P.zstr) ? 1 : 0;
-    P.zoff = P.xonce ? (int32_t)xbytes[L] : 0;
-    big = std::max(big, P.xonce ? xbytes[L] + zbytes[L] : zbytes[L]);
+    P.zoff = P.xonce ? (int32_t)x_tight : 0;
+    big = std::max(big, P.xonce ? x_tight + zbytes[L] : std::max(xbytes[L], zbytes[L]));
   }
   x.big_bytes = (int32_t)big;
-  if (ace_mixed_lds_bytes(x) + 1024 > 160 * 1024)
+  if (ace_mixed_lds_bytes(x) + kLdsReserve > 160 * 1024)
     return fail(ctx, AP_ERR_UNSUPPORTED, "ACE model too large for the mixed kernel's LDS");
   if ((st = upload_owned(ctx, ctile, &x.ctile)) || (st = upload_owned(ctx, rscale, &x.rscale)) ||
       (st = upload_owned(ctx, grp_pat, &x.grp_pat)) || (st = upload_owned(ctx, grp_mem, &x.grp_mem)) ||

@@ -24,11 +24,12 @@ namespace ap {
 template <int L, uint32_t XOMASK>
 __device__ __forceinline__ void fused_rank(const MixDev& m, float* A, float* om1, float* om2,
                                            unsigned char* big, float* phi_lds, const float* bn_lds,
-                                           const int32_t* lv_lds, int32_t* rows_lds, int4* mem_lds,
+                                           const int32_t* lv_lds, int16_t* rows_lds, int4* mem_lds,
                                            int wave, int lane, int tid) {
   const MixL P = load_level_lds(lv_lds + L * kLevelInts);
   const int nidx = m.n_max * (m.l_max + 1);
-  for (int q = tid; q < nidx * nidx; q += kMThreads) rows_lds[q] = m.rowtab[(size_t)L * nidx * nidx + q];
+  for (int q = tid; q < nidx * nidx; q += kMThreads)
+    rows_lds[q] = (int16_t)m.rowtab[(size_t)L * nidx * nidx + q];
   for (int q = tid; q < P.ngrp * 8; q += kMThreads) mem_lds[q] = m.grp_mem[(size_t)P.grp0 * 8 + q];
   float* rs_lds = reinterpret_cast<float*>(mem_lds + P.ngrp * 8);
   for (int q = tid; q < 2 * P.nrow16; q += kMThreads) rs_lds[q] = m.rscale[P.rs0 + q];
@@ -42,7 +43,7 @@ __device__ __forceinline__ void fused_rank(const MixDev& m, float* A, float* om1
 template <int L, int LMAX, uint32_t XOMASK, typename Fetch>
 __device__ __forceinline__ void fused_ranks(const MixDev& m, float* A, float* om1, float* om2,
                                             unsigned char* big, float* phi_lds, const float* bn_lds,
-                                            const int32_t* lv_lds, int32_t* rows_lds, int4* mem_lds,
+                                            const int32_t* lv_lds, int16_t* rows_lds, int4* mem_lds,
                                             int wave, int lane, int tid, Fetch&& fetch_next) {
   if constexpr (L <= LMAX) {
     if constexpr (L == (LMAX > 0 ? LMAX - 1 : 0)) fetch_next();
@@ -67,8 +68,8 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank_fused(
   float* bn_lds = phi_lds + 2 * kMT;                    // [kMT]
   unsigned char* big = lds + m.big_off;
   const int nidx = m.n_max * (m.l_max + 1);
-  int32_t* rows_lds = reinterpret_cast<int32_t*>(lds + m.tab_off);
-  int4* mem_lds = reinterpret_cast<int4*>(rows_lds + nidx * nidx);
+  int16_t* rows_lds = reinterpret_cast<int16_t*>(lds + m.tab_off);
+  int4* mem_lds = reinterpret_cast<int4*>(lds + m.tab_off + (nidx * nidx * 2 + 15) / 16 * 16);
   int32_t* lv_lds = reinterpret_cast<int32_t*>(lds + m.tab_off) - (2 * kMaxL + 1) * kLevelInts;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -145,12 +146,12 @@ __global__ __launch_bounds__(kMThreads, 1) void k_ace_rank_fused(
 }
 
 // Instances for the rank layouts of the two model shapes of the workloads:
-// (n_max 8, l_max 4, nu <= 4): L_max 8, X_L kept at L = 0, 1, 2, 7, 8;
+// (n_max 8, l_max 4, nu <= 4): L_max 8, X_L kept at L = 0, 1, 2, 6, 7, 8;
 // (n_max 6, l_max 3, nu <= 3): L_max 3, X_L kept at every L.
 // Other layouts run one kernel per rank.
 const void* rank_kernel_fused(bool queue, uint32_t xomask, int lmax) {
-  if (xomask == 0x187u && lmax == 8)
-    return queue ? (const void*)k_ace_rank_fused<true, 0x187u, 8> : (const void*)k_ace_rank_fused<false, 0x187u, 8>;
+  if (xomask == 0x1c7u && lmax == 8)
+    return queue ? (const void*)k_ace_rank_fused<true, 0x1c7u, 8> : (const void*)k_ace_rank_fused<false, 0x1c7u, 8>;
   if (xomask == 0xfu && lmax == 3)
     return queue ? (const void*)k_ace_rank_fused<true, 0xfu, 3> : (const void*)k_ace_rank_fused<false, 0xfu, 3>;
   return nullptr;
