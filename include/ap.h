@@ -430,7 +430,11 @@ ap_status ap_profile_read(ap_ctx* ctx, double* ms, int64_t* calls, int32_t n);
  *   "ace.nnz"            non-zeros of the folded coefficient matrices;
  *   "ace.x_rows"         rows of the coupled vectors X_L summed over L;
  *   "ace.a_size"         length of the atomic basis A;
- *   "eam.flops_bond"     FLOPs per bond of the two EAM passes.
+ *   "eam.flops_bond"     FLOPs per bond of the two EAM passes;
+ *   "ace.mfma_tiles"     stored 16x32 coefficient tiles of the mixed path;
+ *   "ace.mfma_flops_atom" executed MFMA FLOPs per ACE atom of the mixed path
+ *                        (three split products over the dense tiles);
+ *   "ace.rank_mode"      launch mode of the last mixed rank phase (-1: none).
  * Returns AP_ERR_ARG for an unknown key. */
 ap_status ap_info(const ap_ctx* ctx, const char* key, double* value);
 
