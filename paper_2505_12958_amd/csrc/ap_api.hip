@@ -1021,7 +1021,7 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&ctx->cell_big, &ctx->pos4, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
-                    &ctx->ace_rows_list, &ctx->rev_ace, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
+                    &ctx->ace_rows_list, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn, &ctx->sw_csp, &ctx->sw_mu0,
                     &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc,
                     &ctx->e_eam_raw, &ctx->e_ace_raw, &ctx->nvt_ke, &ctx->nvt_sums, &ctx->nvt_fac})
@@ -1283,17 +1283,9 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     }
     const int32_t stamp = ++ctx->halo_stamp;
     int32_t* halo = (int32_t*)ctx->ace_halo.p;
-    if (!rev) {
-      // no full reverse index: the slots of the pairs that start at a listed
-      // atom (the same pass stamps the halo)
-      if ((st = ensure(ctx, ctx->rev_ace, 4 * (size_t)nl->capacity * std::max<int64_t>(N, 1)))) return st;
-      AP_HIP(launch_rev_ace((int32_t)N, nl->nbr, nl->count, ace_list, n_ace,
-                            (const int32_t*)ctx->ace_row.p, (int32_t*)ctx->rev_ace.p, halo, stamp, s));
-      rev = (const int32_t*)ctx->rev_ace.p;
-    } else {
-      AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace,
-                             (const int32_t*)ctx->ace_row.p, halo, stamp, s));
-    }
+    // without a full reverse index the gather finds each reverse slot by
+    // binary search of the (ascending) neighbour row
+    AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, halo, stamp, s));
     AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev, nl->capacity,
                              (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
   }

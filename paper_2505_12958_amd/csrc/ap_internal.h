@@ -189,7 +189,7 @@ struct Ctx {
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
-  Buffer ace_row, pair_g, ace_counter, ace_rows_list, rev_ace, ace_halo;
+  Buffer ace_row, pair_g, ace_counter, ace_rows_list, ace_halo;
   int32_t halo_stamp = 0;           // last stamp written into ace_halo (0: cleared)
   Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
   Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
@@ -341,12 +341,9 @@ const void* rank_kernel(bool xo);
 // device work counter instead of round-robin
 const void* rank_kernel_fused(bool queue, uint32_t xomask, int lmax);
 uint32_t rank_xomask(const MixDev& m);
-hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
-                          int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s);
 hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
-                           int32_t* halo, int32_t stamp, hipStream_t s);
+                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
+                           int32_t stamp, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, int32_t cap, const int32_t* ace_row,
                              const int32_t* halo, int32_t stamp, const void* pair_g, double* force,

@@ -302,20 +302,13 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   return hipGetLastError();
 }
 
-// Reverse slots of the pairs that start at an ACE-listed atom only: for
-// listed atom j and slot r (k = nbr[r][j]), rev[s][k] = r where s is the slot
-// of j in the (ascending) list of k.  Entries of pairs whose first atom is
-// not listed are left untouched (the gather never reads them).  One
-// wavefront per listed atom, one lane per slot.
-// One wavefront per listed atom j (grid-stride over the list, whose length
-// is known on the device only), one lane per slot r of j: the slot of j in
-// the row of k = nbr(j, r) by binary search over that ascending row.  The
-// same pass stamps the non-listed k as members of the ACE halo (see
-// k_ace_halo).
-__global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
-                          const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                          const int32_t* __restrict__ row, int32_t* __restrict__ rev,
-                          int32_t* __restrict__ halo, int32_t stamp) {
+// Stamps the atoms whose ACE force sum is not empty: the listed atoms and
+// the atoms in their (full, hence symmetric) neighbour rows.  Every writer
+// stores the same value, so the result does not depend on the order of the
+// writes; a fresh stamp per evaluation makes clearing the array unnecessary.
+__global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
+                           int32_t* __restrict__ halo, int32_t stamp) {
   const int lane = threadIdx.x & 63;
   const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
   const int m = ace_list ? *n_ace : n;
@@ -323,18 +316,8 @@ __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t*
        item += waves) {
     const int j = ace_list ? ace_list[item] : item;
     const int cj = count[j];
-    for (int r = lane; r < cj; r += 64) {
-      const int k = nbr[(int64_t)r * n + j];
-      if (row[k] < 0) halo[k] = stamp;
-      int lo = 0, hi = count[k] - 1, pos = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = nbr[(int64_t)mid * n + k];
-        if (v == j) { pos = mid; break; }
-        if (v < j) lo = mid + 1; else hi = mid - 1;
-      }
-      if (pos >= 0) rev[(int64_t)pos * n + k] = r;
-    }
+    if (lane == 0) halo[j] = stamp;
+    for (int r = lane; r < cj; r += 64) halo[nbr[(int64_t)r * n + j]] = stamp;
   }
 }
 
@@ -342,68 +325,48 @@ __global__ void k_rev_ace(int n, const int32_t* __restrict__ nbr, const int32_t*
 // several times, independent of the total number of atoms
 constexpr int64_t kListWaves = 65536;
 
-hipError_t launch_rev_ace(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                          const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
-                          int32_t* rev, int32_t* halo, int32_t stamp, hipStream_t s) {
-  if (n_atoms == 0) return hipSuccess;
-  const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
-  hipLaunchKernelGGL(k_rev_ace, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, row, rev, halo, stamp);
-  return hipGetLastError();
-}
-
-// Stamps the atoms outside the ACE list whose ACE force sum is not empty: those
-// in the (full, hence symmetric) neighbour rows of listed atoms.  Listed atoms
-// (row >= 0) are always visited by the gather and are not stamped.  Every
-// writer stores the same value, so the result does not depend on the order of
-// the writes; a fresh stamp per evaluation makes clearing the array
-// unnecessary.
-__global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
-                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                           const int32_t* __restrict__ row, int32_t* __restrict__ halo,
-                           int32_t stamp) {
-  const int lane = threadIdx.x & 63;
-  const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
-  const int m = ace_list ? *n_ace : n;
-  for (int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); item < m;
-       item += waves) {
-    const int j = ace_list ? ace_list[item] : item;
-    const int cj = count[j];
-    for (int r = lane; r < cj; r += 64) {
-      const int k = nbr[(int64_t)r * n + j];
-      if (row[k] < 0) halo[k] = stamp;
-    }
-  }
-}
-
 hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, const int32_t* row,
-                           int32_t* halo, int32_t stamp, hipStream_t s) {
+                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
+                           int32_t stamp, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
   hipLaunchKernelGGL(k_ace_halo, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, row, halo, stamp);
+                     nbr, count, ace_list, n_ace, halo, stamp);
   return hipGetLastError();
 }
 
-// F_k = sum_s g(k, s) - sum_s g(nbr(k, s), rev(k, s)), over listed atoms only.
-// Atoms neither listed nor in the halo have no ACE term: zero (or unchanged
-// when accumulating).
-template <typename G>
-__global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
-                             const int32_t* __restrict__ rev, int cap, const int32_t* __restrict__ row,
-                             const int32_t* __restrict__ halo, int32_t stamp,
-                             const G* __restrict__ g, double* __restrict__ force, int accumulate) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// F_k = sum_s g(k, s) - sum_s g(j_s, r_s) over the slots s of k, j_s = nbr(k, s),
+// where g(i, s) is the gradient of the ACE energy of listed atom i with
+// respect to its bond s and r_s is the slot of k in the row of j_s: read from
+// the full reverse index when the list has one (REV), else found by binary
+// search of the ascending row (the same value).  kGatherLanes lanes per atom,
+// lane l taking the slots s = l (mod kGatherLanes); the lanes' partial sums are
+// combined by a fixed butterfly, so the result is the same in every run and
+// with or without the reverse index.  Atoms not stamped for this evaluation
+// have no ACE term: zero, or unchanged when accumulating.
+constexpr int kGatherLanes = 16;
+
+template <typename G, bool REV>
+__global__ __launch_bounds__(256) void k_ace_gather(int n, const int32_t* __restrict__ nbr,
+                                                    const int32_t* __restrict__ count,
+                                                    const int32_t* __restrict__ rev, int cap,
+                                                    const int32_t* __restrict__ row,
+                                                    const int32_t* __restrict__ halo, int32_t stamp,
+                                                    const G* __restrict__ g,
+                                                    double* __restrict__ force, int accumulate) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int k = (int)(t / kGatherLanes);
+  const int l = (int)(t % kGatherLanes);
+  // whole groups leave together: the butterfly below reads only lanes of its group
   if (k >= n) return;
-  const int rk = row[k];
-  if (rk < 0 && halo[k] != stamp) {
-    if (!accumulate) { force[k] = 0.0; force[n + k] = 0.0; force[2 * n + k] = 0.0; }
+  if (halo[k] != stamp) {
+    if (!accumulate && l == 0) { force[k] = 0.0; force[n + k] = 0.0; force[2 * n + k] = 0.0; }
     return;
   }
+  const int rk = row[k];
   const int c = count[k];
   double fx = 0, fy = 0, fz = 0;
-  for (int s = 0; s < c; ++s) {
+  for (int s = l; s < c; s += kGatherLanes) {
     if (rk >= 0) {
       const G* o = g + ((int64_t)rk * cap + s) * 3;
       fx += (double)o[0]; fy += (double)o[1]; fz += (double)o[2];
@@ -411,13 +374,31 @@ __global__ void k_ace_gather(int n, const int32_t* __restrict__ nbr, const int32
     const int j = nbr[(int64_t)s * n + k];
     const int rj = row[j];
     if (rj >= 0) {
-      const int r = rev[(int64_t)s * n + k];
+      int r = -1;
+      if constexpr (REV) {
+        r = rev[(int64_t)s * n + k];
+      } else {
+        int lo = 0, hi = count[j] - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int v = nbr[(int64_t)mid * n + j];
+          if (v == k) { r = mid; break; }
+          if (v < k) lo = mid + 1; else hi = mid - 1;
+        }
+      }
       if (r >= 0) {
         const G* o = g + ((int64_t)rj * cap + r) * 3;
         fx -= (double)o[0]; fy -= (double)o[1]; fz -= (double)o[2];
       }
     }
   }
+#pragma unroll
+  for (int d = kGatherLanes / 2; d >= 1; d >>= 1) {
+    fx += __shfl_xor(fx, d, kGatherLanes);
+    fy += __shfl_xor(fy, d, kGatherLanes);
+    fz += __shfl_xor(fz, d, kGatherLanes);
+  }
+  if (l != 0) return;
   if (accumulate) {
     force[k] += fx; force[n + k] += fy; force[2 * n + k] += fz;
   } else {
@@ -430,13 +411,22 @@ hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, 
                              const int32_t* halo, int32_t stamp, const void* pair_g,
                              double* force, bool accumulate, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
-  const dim3 g((n_atoms + 255) / 256), b(256);
-  if (c.precision == AP_PREC_FP64)
-    hipLaunchKernelGGL(k_ace_gather<double>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
-                       halo, stamp, (const double*)pair_g, force, accumulate ? 1 : 0);
+  const int64_t threads = (int64_t)n_atoms * kGatherLanes;
+  const dim3 g((unsigned)((threads + 255) / 256)), b(256);
+  const int acc = accumulate ? 1 : 0;
+  const bool fp64 = c.precision == AP_PREC_FP64;
+  if (fp64 && rev)
+    hipLaunchKernelGGL((k_ace_gather<double, true>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
+                       ace_row, halo, stamp, (const double*)pair_g, force, acc);
+  else if (fp64)
+    hipLaunchKernelGGL((k_ace_gather<double, false>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
+                       ace_row, halo, stamp, (const double*)pair_g, force, acc);
+  else if (rev)
+    hipLaunchKernelGGL((k_ace_gather<float, true>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
+                       ace_row, halo, stamp, (const float*)pair_g, force, acc);
   else
-    hipLaunchKernelGGL(k_ace_gather<float>, g, b, 0, s, n_atoms, nbr, count, rev, cap, ace_row,
-                       halo, stamp, (const float*)pair_g, force, accumulate ? 1 : 0);
+    hipLaunchKernelGGL((k_ace_gather<float, false>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
+                       ace_row, halo, stamp, (const float*)pair_g, force, acc);
   return hipGetLastError();
 }
 
