@@ -1021,7 +1021,7 @@ ap_status ap_destroy(ap_ctx* c) {
   for (Buffer* b : {&ctx->cell_big, &ctx->pos4, &ctx->cell_count, &ctx->cell_start, &ctx->cell_cursor, &ctx->cell_atoms,
                     &ctx->cell_pos, &ctx->cell_of, &ctx->scan_tmp, &ctx->wfp, &ctx->eF, &ctx->wgt,
                     &ctx->vir_atom, &ctx->e_tmp, &ctx->ace_row, &ctx->pair_g, &ctx->ace_counter,
-                    &ctx->ace_rows_list, &ctx->ace_halo, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
+                    &ctx->ace_rows_list, &ctx->ace_halo, &ctx->nbr_ace, &ctx->partials, &ctx->flags, &ctx->ind_atom, &ctx->mix_A,
                     &ctx->mix_om, &ctx->mix_phi, &ctx->mix_bn, &ctx->sw_csp, &ctx->sw_mu0,
                     &ctx->sw_mu, &ctx->sw_flag, &ctx->sw_src, &ctx->sw_nsrc,
                     &ctx->e_eam_raw, &ctx->e_ace_raw, &ctx->nvt_ke, &ctx->nvt_sums, &ctx->nvt_fac})
@@ -1182,6 +1182,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   if ((st = ensure(ctx, ctx->ace_row, 4 * (size_t)std::max<int64_t>(N, 1))) ||
       (st = ensure(ctx, ctx->ace_counter, 256)) ||
       (st = ensure(ctx, ctx->pair_g, gsz * 3 * (size_t)nl->capacity * std::max<int64_t>(N, 1))) ||
+      (st = ensure(ctx, ctx->nbr_ace, 4 * (size_t)nl->capacity * std::max<int64_t>(N, 1))) ||
       (st = ensure(ctx, ctx->e_ace_raw, 8 * (size_t)std::max<int64_t>(N, 1))) ||
       (virial && (st = ensure(ctx, ctx->vir_atom, 72 * (size_t)N))))
     return st;
@@ -1198,7 +1199,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
                       (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
                       (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir,
-                      (double*)ctx->e_ace_raw.p, s));
+                      (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p, s));
   } else {
     const MixDev& mx = ctx->mix;
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
@@ -1215,7 +1216,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                               nl->capacity, (int32_t)N, lambda, ace_list, n_ace,
                               (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p, (float*)ctx->mix_A.p,
                               (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p, (float*)ctx->mix_bn.p, e_atom,
-                              vir, s, phase, mode, (double*)ctx->e_ace_raw.p);
+                              vir, s, phase, mode, (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p);
     };
     {
       PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
@@ -1284,10 +1285,11 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     const int32_t stamp = ++ctx->halo_stamp;
     int32_t* halo = (int32_t*)ctx->ace_halo.p;
     // without a full reverse index the gather finds each reverse slot by
-    // binary search of the (ascending) neighbour row
+    // binary search of the (ascending) neighbour row, in the atom-major copy
+    // of the listed atoms' rows that the ACE kernels wrote
     AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, halo, stamp, s));
-    AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev, nl->capacity,
-                             (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
+    AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev,
+                             (const int32_t*)ctx->nbr_ace.p, nl->capacity, (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
   }
   if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;

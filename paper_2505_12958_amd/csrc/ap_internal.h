@@ -189,7 +189,7 @@ struct Ctx {
   Buffer cell_count, cell_start, cell_cursor, cell_atoms, cell_pos, cell_of;
   Buffer scan_tmp;
   Buffer wfp, eF, wgt, vir_atom, e_tmp;
-  Buffer ace_row, pair_g, ace_counter, ace_rows_list, ace_halo;
+  Buffer ace_row, pair_g, ace_counter, ace_rows_list, ace_halo, nbr_ace;
   int32_t halo_stamp = 0;           // last stamp written into ace_halo (0: cleared)
   Buffer mix_A, mix_om, mix_phi;        // mixed path: A, adjoint (2 sets), phi per ACE atom
   Buffer mix_bn;                        // mixed path: largest |A_(n,l)|^2 per ACE atom (X scale)
@@ -320,16 +320,17 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
-                      double* e_raw, hipStream_t s);
-// phase 0: bond basis -> A; 1: coupling/contraction/adjoint -> om, phi;
-// 2: embedding, bond gradients, virial
+                      double* e_raw, int32_t* nbr_ace, hipStream_t s);
+// phase 0: bond basis -> A (and the listed atoms' rows, atom-major, ->
+// nbr_ace); 1: coupling/contraction/adjoint -> om, phi; 2: embedding, bond
+// gradients, virial
 hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
                             const int32_t* nbr,
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase, int rank_mode = AP_RANK_FUSED, double* e_raw = nullptr);
+                            int phase, int rank_mode, double* e_raw, int32_t* nbr_ace);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 // the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
 // per L); xo: the variant that keeps X_L in LDS for both coefficient sets
@@ -345,9 +346,9 @@ hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* c
                            const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
                            int32_t stamp, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                             const int32_t* rev, int32_t cap, const int32_t* ace_row,
-                             const int32_t* halo, int32_t stamp, const void* pair_g, double* force,
-                             bool accumulate, hipStream_t s);
+                             const int32_t* rev, const int32_t* nbr_ace, int32_t cap,
+                             const int32_t* ace_row, const int32_t* halo, int32_t stamp,
+                             const void* pair_g, double* force, bool accumulate, hipStream_t s);
 hipError_t launch_ace_rows(int32_t n_atoms, const int32_t* ace_list, const int32_t* n_ace,
                            int32_t* ace_row, hipStream_t s);
 

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir, double* __restrict__ e_raw) {
+    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace) {
   extern __shared__ double lds[];
   const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
   double* A = lds;                               // [nA]
@@ -111,6 +111,7 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
       const int nb = min(kBondChunk, c - base);
       if (tid < nb) {
         const int j = nbr[(int64_t)(base + tid) * n + i];
+        nbr_ace[(int64_t)item * cap + base + tid] = j;  // the row again, atom-major, for the force gather
         const double4 pj = pos4[j];
         double dx, dy, dz;
         displacement(ortho, H, Hi, sv.per, xi, yi, zi, pj.x, pj.y, pj.z, dx, dy, dz);
@@ -283,7 +284,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
-                      double* e_raw, hipStream_t s) {
+                      double* e_raw, int32_t* nbr_ace, hipStream_t s) {
   (void)ace_row;
   hipError_t e = hipSuccess;
   int dev = 0, n_cu = 256;
@@ -298,7 +299,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   }
   hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, pos4, nbr,
                      count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
-                     vir_atom, e_raw);
+                     vir_atom, e_raw, nbr_ace);
   return hipGetLastError();
 }
 
@@ -339,17 +340,20 @@ hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* c
 // where g(i, s) is the gradient of the ACE energy of listed atom i with
 // respect to its bond s and r_s is the slot of k in the row of j_s: read from
 // the full reverse index when the list has one (REV), else found by binary
-// search of the ascending row (the same value).  kGatherLanes lanes per atom,
+// search of j_s's ascending row in the atom-major copy the ACE kernels wrote
+// (nbr_ace, one row of cap entries per listed atom, so a search stays within
+// a few cache lines); both give the same value.  kGatherLanes lanes per atom,
 // lane l taking the slots s = l (mod kGatherLanes); the lanes' partial sums are
 // combined by a fixed butterfly, so the result is the same in every run and
 // with or without the reverse index.  Atoms not stamped for this evaluation
 // have no ACE term: zero, or unchanged when accumulating.
-constexpr int kGatherLanes = 16;
+constexpr int kGatherLanes = 4;
 
 template <typename G, bool REV>
 __global__ __launch_bounds__(256) void k_ace_gather(int n, const int32_t* __restrict__ nbr,
                                                     const int32_t* __restrict__ count,
-                                                    const int32_t* __restrict__ rev, int cap,
+                                                    const int32_t* __restrict__ rev,
+                                                    const int32_t* __restrict__ nbr_ace, int cap,
                                                     const int32_t* __restrict__ row,
                                                     const int32_t* __restrict__ halo, int32_t stamp,
                                                     const G* __restrict__ g,
@@ -378,10 +382,11 @@ __global__ __launch_bounds__(256) void k_ace_gather(int n, const int32_t* __rest
       if constexpr (REV) {
         r = rev[(int64_t)s * n + k];
       } else {
+        const int32_t* rowj = nbr_ace + (int64_t)rj * cap;
         int lo = 0, hi = count[j] - 1;
         while (lo <= hi) {
           const int mid = (lo + hi) >> 1;
-          const int v = nbr[(int64_t)mid * n + j];
+          const int v = rowj[mid];
           if (v == k) { r = mid; break; }
           if (v < k) lo = mid + 1; else hi = mid - 1;
         }
@@ -407,26 +412,26 @@ __global__ __launch_bounds__(256) void k_ace_gather(int n, const int32_t* __rest
 }
 
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                             const int32_t* rev, int32_t cap, const int32_t* ace_row,
-                             const int32_t* halo, int32_t stamp, const void* pair_g,
-                             double* force, bool accumulate, hipStream_t s) {
+                             const int32_t* rev, const int32_t* nbr_ace, int32_t cap,
+                             const int32_t* ace_row, const int32_t* halo, int32_t stamp,
+                             const void* pair_g, double* force, bool accumulate, hipStream_t s) {
   if (n_atoms == 0) return hipSuccess;
   const int64_t threads = (int64_t)n_atoms * kGatherLanes;
   const dim3 g((unsigned)((threads + 255) / 256)), b(256);
   const int acc = accumulate ? 1 : 0;
   const bool fp64 = c.precision == AP_PREC_FP64;
   if (fp64 && rev)
-    hipLaunchKernelGGL((k_ace_gather<double, true>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
-                       ace_row, halo, stamp, (const double*)pair_g, force, acc);
+    hipLaunchKernelGGL((k_ace_gather<double, true>), g, b, 0, s, n_atoms, nbr, count, rev, nbr_ace,
+                       cap, ace_row, halo, stamp, (const double*)pair_g, force, acc);
   else if (fp64)
-    hipLaunchKernelGGL((k_ace_gather<double, false>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
-                       ace_row, halo, stamp, (const double*)pair_g, force, acc);
+    hipLaunchKernelGGL((k_ace_gather<double, false>), g, b, 0, s, n_atoms, nbr, count, rev, nbr_ace,
+                       cap, ace_row, halo, stamp, (const double*)pair_g, force, acc);
   else if (rev)
-    hipLaunchKernelGGL((k_ace_gather<float, true>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
-                       ace_row, halo, stamp, (const float*)pair_g, force, acc);
+    hipLaunchKernelGGL((k_ace_gather<float, true>), g, b, 0, s, n_atoms, nbr, count, rev, nbr_ace,
+                       cap, ace_row, halo, stamp, (const float*)pair_g, force, acc);
   else
-    hipLaunchKernelGGL((k_ace_gather<float, false>), g, b, 0, s, n_atoms, nbr, count, rev, cap,
-                       ace_row, halo, stamp, (const float*)pair_g, force, acc);
+    hipLaunchKernelGGL((k_ace_gather<float, false>), g, b, 0, s, n_atoms, nbr, count, rev, nbr_ace,
+                       cap, ace_row, halo, stamp, (const float*)pair_g, force, acc);
   return hipGetLastError();
 }
 
