@@ -259,7 +259,8 @@ def roofline_model(ctx, ap, wl, n_ace, n_bonds, n_bonds_ace, fp64):
         # contraction's split products on MFMA (charged in sequence)
         ph["ace_rank_valu"] = ace_valu * n_ace / valu
         ph["ace_rank_mfma"] = SPLIT_PRODUCTS * ctx.info("ace.flops_contract") * n_ace / mfma
-    # gather: per ACE bond the pair gradient (12 B) and reverse slot (4 B), per atom the force
+    # gather: per ACE bond the pair gradient (12 B) and 4 B of reverse-slot lookup (the atom-major
+    # row copy the basis pass writes), per atom the force
     ph["ace_gather"] = (n_bonds_ace * 16 + N * 24) / hbm
     ph["indenter"] = N * (24 + 1 + 24) / hbm
     ph["integrate"] = 2 * N * (24 * 3 + 8 + 1) / hbm
