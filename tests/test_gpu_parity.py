@@ -68,16 +68,15 @@ def test_reverse_slots(name):
 
 @pytest.mark.parametrize("precision", [ap.AP_PREC_FP64, ap.AP_PREC_MIXED])
 def test_forces_without_full_reverse_index(precision):
-    """ACE forces from lists built without rev (reverse slots derived for the
-    ACE pairs only) equal those with the full index, bit for bit."""
+    """ACE forces from lists built without rev (the gather finds each reverse
+    slot by binary search) equal those with the full index, bit for bit, in
+    both precisions: the slots are the same and so is the order of the sums."""
     wl, _ = oracle("wslab10")
     a = run_force(wl, precision=precision, with_rev=True)
     b = run_force(wl, precision=precision, with_rev=False)
-    assert np.array_equal(a["forces"], b["forces"]) or precision == ap.AP_PREC_MIXED
-    if precision == ap.AP_PREC_MIXED:
-        scale = np.linalg.norm(a["forces"])
-        assert np.linalg.norm(a["forces"] - b["forces"]) / scale <= 1e-6
-    assert np.array_equal(a["e_atom"], b["e_atom"]) or precision == ap.AP_PREC_MIXED
+    assert np.array_equal(a["forces"], b["forces"])
+    assert np.array_equal(a["e_atom"], b["e_atom"])
+    assert np.array_equal(a["virial"], b["virial"])
 
 
 @pytest.mark.parametrize("name", CASES)
