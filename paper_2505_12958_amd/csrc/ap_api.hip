@@ -1060,10 +1060,9 @@ ap_status ap_build_neighbors(ap_ctx* c, const ap_systems* sys, const double* pos
   if (needed_capacity) AP_HIP(launch_fill_i32(flags, 0, 1, s));
   AP_HIP(launch_fill_i32((int32_t*)ctx->cell_count.p, 0, nc, s));
   AP_HIP(launch_bin(sv, pos, (int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_count.p, s));
+  // the scan also writes the scatter's cursors (a copy of the cell starts)
   AP_HIP(launch_scan_exclusive((const int32_t*)ctx->cell_count.p, (int32_t*)ctx->cell_start.p, nc,
-                               (int32_t*)ctx->scan_tmp.p, s));
-  AP_HIP(hipMemcpyAsync(ctx->cell_cursor.p, ctx->cell_start.p, 4 * (size_t)nc,
-                        hipMemcpyDeviceToDevice, s));
+                               (int32_t*)ctx->scan_tmp.p, s, (int32_t*)ctx->cell_cursor.p));
   AP_HIP(launch_scatter(sv, pos, (const int32_t*)ctx->cell_of.p, (int32_t*)ctx->cell_cursor.p,
                         (int32_t*)ctx->cell_atoms.p, (double4*)ctx->cell_pos.p, s));
   AP_HIP(launch_fill_nbr_cells(sv, nc, pos, (const int32_t*)ctx->cell_of.p,
@@ -1119,14 +1118,17 @@ ap_status ap_blend(ap_ctx* c, const ap_systems* sys, const double* pos, const ap
   return AP_OK;
 }
 
+// copy0/copy1 (optional) receive system 0's first and second sums as well
 static ap_status reduce_into(Ctx* ctx, const SysView& sv, const double* vals, int m, double* out,
-                             bool accumulate, hipStream_t s) {
+                             bool accumulate, hipStream_t s, double* copy0 = nullptr,
+                             double* copy1 = nullptr) {
   ap_status st;
   PhaseTimer timer(ctx, AP_PHASE_REDUCE, s);
   if ((st = scratch_reduce(ctx, m))) return st;
   AP_HIP(launch_reduce(sv, ctx->sys.n_chunks, (const int64_t*)ctx->sys.chunk_lo_d.p,
                        (const int64_t*)ctx->sys.chunk_hi_d.p, (const int32_t*)ctx->sys.sys_chunk_d.p,
-                       vals, m, sv.n_atoms, (double*)ctx->partials.p, out, accumulate, s));
+                       vals, m, sv.n_atoms, (double*)ctx->partials.p, out, accumulate, s, copy0,
+                       copy1));
   return AP_OK;
 }
 
@@ -1194,12 +1196,25 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
   AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
+  // the ACE kernels stamp the listed atoms and their neighbours (the atoms the
+  // gather visits) in the halo array with a fresh stamp per evaluation; a new
+  // allocation, or the stamp running out of range, clears it once.  A stale
+  // entry equal to the current stamp would only make the gather visit an atom
+  // whose ACE sum is zero, so correctness never depends on the clear.
+  const void* halo_before = ctx->ace_halo.p;
+  if ((st = ensure(ctx, ctx->ace_halo, 4 * (size_t)std::max<int64_t>(N, 1)))) return st;
+  if (ctx->ace_halo.p != halo_before || ctx->halo_stamp == INT32_MAX) {
+    AP_HIP(launch_fill_i32((int32_t*)ctx->ace_halo.p, 0, (int32_t)(ctx->ace_halo.bytes / 4), s));
+    ctx->halo_stamp = 0;
+  }
+  const int32_t stamp = ++ctx->halo_stamp;
+  int32_t* halo = (int32_t*)ctx->ace_halo.p;
   if (ctx->precision == AP_PREC_FP64) {
     PhaseTimer timer(ctx, AP_PHASE_ACE, s);
     AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
                       (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
                       (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir,
-                      (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p, s));
+                      (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p, halo, stamp, s));
   } else {
     const MixDev& mx = ctx->mix;
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
@@ -1216,7 +1231,8 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                               nl->capacity, (int32_t)N, lambda, ace_list, n_ace,
                               (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p, (float*)ctx->mix_A.p,
                               (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p, (float*)ctx->mix_bn.p, e_atom,
-                              vir, s, phase, mode, (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p);
+                              vir, s, phase, mode, (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p,
+                              halo, stamp);
     };
     {
       PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
@@ -1272,22 +1288,9 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   {
     PhaseTimer timer(ctx, AP_PHASE_ACE_GATHER, s);
     const int32_t* rev = nl->rev;
-    // the halo array holds a stamp per atom; a new allocation, or the stamp
-    // running out of range, clears it once.  A stale entry equal to the
-    // current stamp would only make the gather visit an atom whose ACE sum is
-    // zero, so correctness never depends on the clear.
-    const void* halo_before = ctx->ace_halo.p;
-    if ((st = ensure(ctx, ctx->ace_halo, 4 * (size_t)std::max<int64_t>(N, 1)))) return st;
-    if (ctx->ace_halo.p != halo_before || ctx->halo_stamp == INT32_MAX) {
-      AP_HIP(launch_fill_i32((int32_t*)ctx->ace_halo.p, 0, (int32_t)(ctx->ace_halo.bytes / 4), s));
-      ctx->halo_stamp = 0;
-    }
-    const int32_t stamp = ++ctx->halo_stamp;
-    int32_t* halo = (int32_t*)ctx->ace_halo.p;
     // without a full reverse index the gather finds each reverse slot by
     // binary search of the (ascending) neighbour row, in the atom-major copy
     // of the listed atoms' rows that the ACE kernels wrote
-    AP_HIP(launch_ace_halo((int32_t)N, nl->nbr, nl->count, ace_list, n_ace, halo, stamp, s));
     AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev,
                              (const int32_t*)ctx->nbr_ace.p, nl->capacity, (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
   }
@@ -1316,9 +1319,7 @@ ap_status ap_indenter(ap_ctx* c, const ap_systems* sys, const double* pos, const
   AP_HIP(launch_indenter((int32_t)N, pos, fixed, centre, R, K, dir, force, e2, s));
   if (want) {
     double* out = (double*)ctx->ind_atom.p + 2 * N;
-    if ((st = reduce_into(ctx, sv, e2, 2, out, false, s))) return st;
-    if (e_ind) AP_HIP(hipMemcpyAsync(e_ind, out, 8, hipMemcpyDeviceToDevice, s));
-    if (load) AP_HIP(hipMemcpyAsync(load, out + 1, 8, hipMemcpyDeviceToDevice, s));
+    if ((st = reduce_into(ctx, sv, e2, 2, out, false, s, e_ind, load))) return st;
   }
   return AP_OK;
 }

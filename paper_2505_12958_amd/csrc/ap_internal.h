@@ -253,7 +253,7 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 hipError_t launch_bin(const SysView& sv, const double* pos, int32_t* cell_of, int32_t* cell_count,
                       hipStream_t s);
 hipError_t launch_scan_exclusive(const int32_t* in, int32_t* out, int32_t n, int32_t* tmp,
-                                 hipStream_t s);
+                                 hipStream_t s, int32_t* out2 = nullptr);
 hipError_t launch_scatter(const SysView& sv, const double* pos, const int32_t* cell_of,
                           int32_t* cursor, int32_t* cell_atoms, double4* cell_pos, hipStream_t s);
 hipError_t launch_fill_nbr_cells(const SysView& sv, int32_t n_cells, const double* pos,
@@ -277,7 +277,7 @@ hipError_t launch_seq(int32_t n, int32_t* out, hipStream_t s);
 hipError_t launch_reduce(const SysView& sv, int32_t n_chunks, const int64_t* chunk_lo,
                          const int64_t* chunk_hi, const int32_t* sys_chunk, const double* vals,
                          int32_t m, int64_t stride, double* partials, double* out, bool accumulate,
-                         hipStream_t s);
+                         hipStream_t s, double* copy0 = nullptr, double* copy1 = nullptr);
 // indenter / integration / checks
 hipError_t launch_indenter(int32_t n, const double* pos, const uint8_t* fixed, const double* c,
                            double R, double K, const double* dir, double* force, double* e_atom2,
@@ -320,17 +320,19 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
-                      double* e_raw, int32_t* nbr_ace, hipStream_t s);
+                      double* e_raw, int32_t* nbr_ace, int32_t* halo, int32_t stamp,
+                      hipStream_t s);
 // phase 0: bond basis -> A (and the listed atoms' rows, atom-major, ->
-// nbr_ace); 1: coupling/contraction/adjoint -> om, phi; 2: embedding, bond
-// gradients, virial
+// nbr_ace; the listed atoms and their neighbours stamped in halo); 1:
+// coupling/contraction/adjoint -> om, phi; 2: embedding, bond gradients, virial
 hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, const double4* pos4,
                             const int32_t* nbr,
                             const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase, int rank_mode, double* e_raw, int32_t* nbr_ace);
+                            int phase, int rank_mode, double* e_raw, int32_t* nbr_ace,
+                            int32_t* halo, int32_t stamp);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 // the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
 // per L); xo: the variant that keeps X_L in LDS for both coefficient sets
@@ -342,9 +344,6 @@ const void* rank_kernel(bool xo);
 // device work counter instead of round-robin
 const void* rank_kernel_fused(bool queue, uint32_t xomask, int lmax);
 uint32_t rank_xomask(const MixDev& m);
-hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
-                           int32_t stamp, hipStream_t s);
 hipError_t launch_ace_gather(const Ctx& c, int32_t n_atoms, const int32_t* nbr, const int32_t* count,
                              const int32_t* rev, const int32_t* nbr_ace, int32_t cap,
                              const int32_t* ace_row, const int32_t* halo, int32_t stamp,

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace) {
+    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace,
+    int32_t* __restrict__ halo, int32_t stamp) {
   extern __shared__ double lds[];
   const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
   double* A = lds;                               // [nA]
@@ -105,13 +106,16 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     const int c = count[i];
 
-    // ---- atomic basis A
+    // ---- atomic basis A (the atom and its neighbours carry an ACE force
+    // term: stamped for the gather)
+    if (tid == 0) halo[i] = stamp;
     for (int e = tid; e < nA; e += kAceThreads) { A[e] = 0.0; om1[e] = 0.0; om2[e] = 0.0; }
     for (int base = 0; base < c; base += kBondChunk) {
       const int nb = min(kBondChunk, c - base);
       if (tid < nb) {
         const int j = nbr[(int64_t)(base + tid) * n + i];
         nbr_ace[(int64_t)item * cap + base + tid] = j;  // the row again, atom-major, for the force gather
+        halo[j] = stamp;
         const double4 pj = pos4[j];
         double dx, dy, dz;
         displacement(ortho, H, Hi, sv.per, xi, yi, zi, pj.x, pj.y, pj.z, dx, dy, dz);
@@ -284,7 +288,8 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* count, int32_t cap, int32_t n_atoms, const double* lambda,
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
-                      double* e_raw, int32_t* nbr_ace, hipStream_t s) {
+                      double* e_raw, int32_t* nbr_ace, int32_t* halo, int32_t stamp,
+                      hipStream_t s) {
   (void)ace_row;
   hipError_t e = hipSuccess;
   int dev = 0, n_cu = 256;
@@ -299,40 +304,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   }
   hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, pos4, nbr,
                      count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
-                     vir_atom, e_raw, nbr_ace);
-  return hipGetLastError();
-}
-
-// Stamps the atoms whose ACE force sum is not empty: the listed atoms and
-// the atoms in their (full, hence symmetric) neighbour rows.  Every writer
-// stores the same value, so the result does not depend on the order of the
-// writes; a fresh stamp per evaluation makes clearing the array unnecessary.
-__global__ void k_ace_halo(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
-                           const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
-                           int32_t* __restrict__ halo, int32_t stamp) {
-  const int lane = threadIdx.x & 63;
-  const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
-  const int m = ace_list ? *n_ace : n;
-  for (int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); item < m;
-       item += waves) {
-    const int j = ace_list ? ace_list[item] : item;
-    const int cj = count[j];
-    if (lane == 0) halo[j] = stamp;
-    for (int r = lane; r < cj; r += 64) halo[nbr[(int64_t)r * n + j]] = stamp;
-  }
-}
-
-// waves of the grid-stride kernels over the ACE list: enough to fill the chip
-// several times, independent of the total number of atoms
-constexpr int64_t kListWaves = 65536;
-
-hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* count,
-                           const int32_t* ace_list, const int32_t* n_ace, int32_t* halo,
-                           int32_t stamp, hipStream_t s) {
-  if (n_atoms == 0) return hipSuccess;
-  const int64_t threads = std::min<int64_t>(n_atoms, kListWaves) * 64;
-  hipLaunchKernelGGL(k_ace_halo, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
-                     nbr, count, ace_list, n_ace, halo, stamp);
+                     vir_atom, e_raw, nbr_ace, halo, stamp);
   return hipGetLastError();
 }
 
@@ -346,7 +318,8 @@ hipError_t launch_ace_halo(int32_t n_atoms, const int32_t* nbr, const int32_t* c
 // lane l taking the slots s = l (mod kGatherLanes); the lanes' partial sums are
 // combined by a fixed butterfly, so the result is the same in every run and
 // with or without the reverse index.  Atoms not stamped for this evaluation
-// have no ACE term: zero, or unchanged when accumulating.
+// (the ACE kernels stamp every listed atom and its neighbours) have no ACE
+// term: zero, or unchanged when accumulating.
 constexpr int kGatherLanes = 4;
 
 template <typename G, bool REV>

@@ -21,7 +21,8 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ count, int cap,
     const int32_t* __restrict__ ace_list,
     const int32_t* __restrict__ n_ace_p, int n_all, float* __restrict__ A_out,
-    float* __restrict__ bn_out, int32_t* __restrict__ nbr_ace) {
+    float* __restrict__ bn_out, int32_t* __restrict__ nbr_ace, int32_t* __restrict__ halo,
+    int32_t stamp) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -44,12 +45,15 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_basis(
   float acc[(kMaxN * kMaxLM + 63) / 64];
 #pragma unroll
   for (int q = 0; q < (kMaxN * kMaxLM + 63) / 64; ++q) acc[q] = 0.f;
+  // the atom and its neighbours carry an ACE force term: stamped for the gather
+  if (lane == 0) halo[a] = stamp;
   for (int base = 0; base < c; base += 64) {
     const int s = base + lane;
     float* o = RY + lane * stride;
     if (s < c) {
       const int j = nbr[(int64_t)s * n + a];
       nbr_ace[(int64_t)item * cap + s] = j;  // the row again, atom-major, for the force gather
+      halo[j] = stamp;
       double dx, dy, dz;
       displacement(sv.ortho[sy] != 0, sv.H + 9 * sy, sv.Hi + 9 * sy, sv.per, pos[a], pos[n + a],
                    pos[2 * n + a], pos4[j].x, pos4[j].y, pos4[j].z, dx, dy, dz);
@@ -257,7 +261,8 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             const int32_t* ace_list, const int32_t* n_ace, int32_t* counter,
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
-                            int phase, int rank_mode, double* e_raw, int32_t* nbr_ace) {
+                            int phase, int rank_mode, double* e_raw, int32_t* nbr_ace,
+                            int32_t* halo, int32_t stamp) {
   const MixDev& m = c.mix;
   // grids are sized for every atom; wavefronts past *n_ace leave at once
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
@@ -266,7 +271,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     const size_t lds = (size_t)kBasisWaves * 64 * (m.K + m.nlm) * 4;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
-                         count, cap, ace_list, n_ace, n_atoms, A_buf, bn_buf, nbr_ace);
+                         count, cap, ace_list, n_ace, n_atoms, A_buf, bn_buf, nbr_ace, halo, stamp);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_basis<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_basis<6, 3, 6>);

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t* __restrict__ sums, 
 template <int MODE>
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __restrict__ in, int n,
                                                             const int32_t* __restrict__ offs,
-                                                            int32_t* __restrict__ out) {
+                                                            int32_t* __restrict__ out,
+                                                            int32_t* __restrict__ out2) {
   __shared__ int ws[kScanThreads / 64];
   const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -86,6 +87,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __res
     if (i < n) {
       if (MODE == 0) {
         out[i] = run;
+        if (out2) out2[i] = run;
       } else if (v[k]) {
         out[run] = i;
       }
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t* __res
 }
 
 static hipError_t scan_impl(const int32_t* in, int32_t n, int32_t* out, int32_t* total,
-                            int32_t* tmp, int mode, hipStream_t s) {
+                            int32_t* tmp, int mode, hipStream_t s, int32_t* out2 = nullptr) {
   const int nt = (n + kScanTile - 1) / kScanTile;
   if (nt == 0) {
     if (total) {
@@ -106,16 +108,18 @@ static hipError_t scan_impl(const int32_t* in, int32_t n, int32_t* out, int32_t*
   hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, nt, total);
   if (mode == 0)
-    hipLaunchKernelGGL(k_tile_scan<0>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out);
+    hipLaunchKernelGGL(k_tile_scan<0>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out, out2);
   else
-    hipLaunchKernelGGL(k_tile_scan<1>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out);
+    hipLaunchKernelGGL(k_tile_scan<1>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, out,
+                       (int32_t*)nullptr);
   return hipGetLastError();
 }
 
-// tmp must hold ceil(n / 4096) + 1 ints
+// tmp must hold ceil(n / 4096) + 1 ints; out2 (optional) receives a second
+// copy of the scan
 hipError_t launch_scan_exclusive(const int32_t* in, int32_t* out, int32_t n, int32_t* tmp,
-                                 hipStream_t s) {
-  return scan_impl(in, n, out, nullptr, tmp, 0, s);
+                                 hipStream_t s, int32_t* out2) {
+  return scan_impl(in, n, out, nullptr, tmp, 0, s, out2);
 }
 
 hipError_t launch_compact(int32_t n, const int32_t* flag, int32_t* out_list, int32_t* out_n,
@@ -192,25 +196,29 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const int64_t* __restrict
 
 __global__ void k_reduce_systems(int n_sys, const int32_t* __restrict__ sys_chunk, int m,
                                  const double* __restrict__ partials, double* __restrict__ out,
-                                 int accumulate) {
+                                 int accumulate, double* __restrict__ copy0,
+                                 double* __restrict__ copy1) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_sys * m) return;
   const int s = t / m, k = t % m;
   double v = 0.0;
   for (int c = sys_chunk[s]; c < sys_chunk[s + 1]; ++c) v += partials[(int64_t)c * m + k];
-  out[t] = accumulate ? out[t] + v : v;
+  const double r = accumulate ? out[t] + v : v;
+  out[t] = r;
+  if (t == 0 && copy0) *copy0 = r;
+  if (t == 1 && copy1) *copy1 = r;
 }
 
 hipError_t launch_reduce(const SysView& sv, int32_t n_chunks, const int64_t* chunk_lo,
                          const int64_t* chunk_hi, const int32_t* sys_chunk, const double* vals,
                          int32_t m, int64_t stride, double* partials, double* out, bool accumulate,
-                         hipStream_t s) {
+                         hipStream_t s, double* copy0, double* copy1) {
   if (n_chunks > 0)
     hipLaunchKernelGGL(k_reduce_chunks, dim3(n_chunks, m), dim3(256), 0, s, chunk_lo, chunk_hi,
                        vals, m, stride, partials);
   const int nt = sv.n_sys * m;
   hipLaunchKernelGGL(k_reduce_systems, dim3((nt + 255) / 256), dim3(256), 0, s, sv.n_sys,
-                     sys_chunk, m, partials, out, accumulate ? 1 : 0);
+                     sys_chunk, m, partials, out, accumulate ? 1 : 0, copy0, copy1);
   return hipGetLastError();
 }
 
