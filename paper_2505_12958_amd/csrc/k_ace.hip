@@ -69,8 +69,7 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace,
-    int32_t* __restrict__ halo, int32_t stamp) {
+    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace) {
   extern __shared__ double lds[];
   const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
   double* A = lds;                               // [nA]
@@ -106,16 +105,13 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     const int c = count[i];
 
-    // ---- atomic basis A (the atom and its neighbours carry an ACE force
-    // term: stamped for the gather)
-    if (tid == 0) halo[i] = stamp;
+    // ---- atomic basis A
     for (int e = tid; e < nA; e += kAceThreads) { A[e] = 0.0; om1[e] = 0.0; om2[e] = 0.0; }
     for (int base = 0; base < c; base += kBondChunk) {
       const int nb = min(kBondChunk, c - base);
       if (tid < nb) {
         const int j = nbr[(int64_t)(base + tid) * n + i];
         nbr_ace[(int64_t)item * cap + base + tid] = j;  // the row again, atom-major, for the force gather
-        halo[j] = stamp;
         const double4 pj = pos4[j];
         double dx, dy, dz;
         displacement(ortho, H, Hi, sv.per, xi, yi, zi, pj.x, pj.y, pj.z, dx, dy, dz);
@@ -263,6 +259,25 @@ size_t ace_lds_bytes(const AceDev& a, int precision) {
   return sizeof(double) * (3 * (size_t)a.nA + 16 + shared);
 }
 
+// Stamps the listed atoms and their neighbours (the atoms the force gather
+// visits) for the FP64 path; the mixed path stamps them in its basis pass.
+// Stamping inside k_ace_fp64 slowed that kernel by 7 %, so it has a pass of
+// its own: one wavefront per listed atom, one lane per slot.
+__global__ void k_ace_stamp(int n, const int32_t* __restrict__ nbr, const int32_t* __restrict__ count,
+                            const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace,
+                            int32_t* __restrict__ halo, int32_t stamp) {
+  const int lane = threadIdx.x & 63;
+  const int waves = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
+  const int m = ace_list ? *n_ace : n;
+  for (int item = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); item < m;
+       item += waves) {
+    const int j = ace_list ? ace_list[item] : item;
+    const int cj = count[j];
+    if (lane == 0) halo[j] = stamp;
+    for (int r = lane; r < cj; r += 64) halo[nbr[(int64_t)r * n + j]] = stamp;
+  }
+}
+
 __global__ void k_ace_rows(int n, const int32_t* __restrict__ ace_list,
                            const int32_t* __restrict__ n_ace, int32_t* __restrict__ row) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,6 +312,12 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds = ace_lds_bytes(c.ace, c.precision);
   const int blocks = n_cu * 2;
+  if (n_atoms > 0) {
+    // enough wavefronts to fill the chip several times over the list
+    const int64_t threads = std::min<int64_t>(n_atoms, 65536) * 64;
+    hipLaunchKernelGGL(k_ace_stamp, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, n_atoms,
+                       nbr, count, ace_list, n_ace, halo, stamp);
+  }
   if (lds > 65536) {
     e = hipFuncSetAttribute((const void*)k_ace_fp64, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
@@ -304,7 +325,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   }
   hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, pos4, nbr,
                      count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
-                     vir_atom, e_raw, nbr_ace, halo, stamp);
+                     vir_atom, e_raw, nbr_ace);
   return hipGetLastError();
 }
 
