@@ -1160,7 +1160,8 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                     lambda, (double*)ctx->wfp.p, (double*)ctx->eF.p, (double*)ctx->wgt.p, e_atom,
                     force, vir, acc, (double*)ctx->e_eam_raw.p, s));
   }
-  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
+  // in a fused evaluation the ACE call reduces the EAM and ACE per-atom virials together
+  if (virial && !ctx->fuse_virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
 }
 
@@ -1191,7 +1192,9 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   const bool acc = flags == AP_ACCUMULATE;
   double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
   if (!acc) AP_HIP(launch_fill_f64(e_atom, 0.0, N, s));
-  if (vir) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
+  // a fused evaluation adds the ACE per-atom virial to the EAM call's
+  const bool vir_acc = vir && ctx->fuse_virial;
+  if (vir && !vir_acc) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
   if ((st = ensure(ctx, ctx->pos4, 32 * (size_t)std::max<int64_t>(N, 1)))) return st;
   AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
@@ -1214,7 +1217,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
                       (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
                       (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir,
-                      (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p, halo, stamp, s));
+                      (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p, halo, stamp, vir_acc, s));
   } else {
     const MixDev& mx = ctx->mix;
     const size_t rows = (size_t)std::max<int64_t>(N, 1) + 8;
@@ -1232,7 +1235,7 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                               (int32_t*)ctx->ace_counter.p, (float*)ctx->pair_g.p, (float*)ctx->mix_A.p,
                               (float*)ctx->mix_om.p, (float*)ctx->mix_phi.p, (float*)ctx->mix_bn.p, e_atom,
                               vir, s, phase, mode, (double*)ctx->e_ace_raw.p, (int32_t*)ctx->nbr_ace.p,
-                              halo, stamp);
+                              halo, stamp, vir_acc);
     };
     {
       PhaseTimer timer(ctx, AP_PHASE_ACE_BOND, s);
@@ -1294,7 +1297,8 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
     AP_HIP(launch_ace_gather(*ctx, (int32_t)N, nl->nbr, nl->count, rev,
                              (const int32_t*)ctx->nbr_ace.p, nl->capacity, (const int32_t*)ctx->ace_row.p, halo, stamp, ctx->pair_g.p, force, acc, s));
   }
-  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
+  // fused: the per-atom virial holds EAM + ACE and the system virial is written afresh
+  if (virial && (st = reduce_into(ctx, sv, vir, 9, virial, vir_acc ? false : acc, s))) return st;
   return AP_OK;
 }
 
@@ -1526,18 +1530,26 @@ static ap_status force_eval(Ctx* ctx, const ap_systems* sys, ap_md_state* st, hi
     if ((r = ap_build_neighbors((ap_ctx*)ctx, sys, st->pos, &st->nl, nullptr, s))) return r;
   }
   bool written = false;
-  if (ctx->has_eam) {
-    if ((r = ap_eam_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->e_atom, st->force,
-                           st->virial, AP_OVERWRITE, s)))
-      return r;
-    written = true;
-  }
-  if (ctx->has_ace) {
-    if ((r = ap_ace_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->ace_list, st->n_ace,
-                           st->e_atom, st->force, st->virial, written ? AP_ACCUMULATE : AP_OVERWRITE,
-                           s)))
-      return r;
-    written = true;
+  {
+    // EAM then ACE: one reduction of their summed per-atom virials
+    struct Unfuse {
+      Ctx* c;
+      ~Unfuse() { c->fuse_virial = false; }
+    } unfuse{ctx};
+    ctx->fuse_virial = ctx->has_eam && ctx->has_ace && st->virial != nullptr;
+    if (ctx->has_eam) {
+      if ((r = ap_eam_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->e_atom, st->force,
+                             st->virial, AP_OVERWRITE, s)))
+        return r;
+      written = true;
+    }
+    if (ctx->has_ace) {
+      if ((r = ap_ace_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->ace_list, st->n_ace,
+                             st->e_atom, st->force, st->virial, written ? AP_ACCUMULATE : AP_OVERWRITE,
+                             s)))
+        return r;
+      written = true;
+    }
   }
   if (!written) {
     AP_HIP(launch_fill_f64(st->force, 0.0, 3 * N, s));

@@ -209,6 +209,9 @@ struct Ctx {
   std::string tune_cache;               // cache file path ("" = none)
   int last_rank_mode = -1;
   size_t ace_lds = 0;
+  // set by ap_step's force evaluation: the EAM call leaves its per-atom virial
+  // unreduced and the ACE call adds to it and reduces both at once
+  bool fuse_virial = false;
   // algorithmic work counts (ap_info)
   double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
   double mix_tiles = 0;        // stored 16x32 coefficient tiles (mixed path)
@@ -321,7 +324,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
                       double* e_raw, int32_t* nbr_ace, int32_t* halo, int32_t stamp,
-                      hipStream_t s);
+                      bool vir_acc, hipStream_t s);
 // phase 0: bond basis -> A (and the listed atoms' rows, atom-major, ->
 // nbr_ace; the listed atoms and their neighbours stamped in halo); 1:
 // coupling/contraction/adjoint -> om, phi; 2: embedding, bond gradients, virial
@@ -332,7 +335,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
                             int phase, int rank_mode, double* e_raw, int32_t* nbr_ace,
-                            int32_t* halo, int32_t stamp);
+                            int32_t* halo, int32_t stamp, bool vir_acc);
 size_t ace_mixed_lds_bytes(const MixDev& m);
 // the rank kernel of coupled rank L (k_ace_rank.hip, one translation unit
 // per L); xo: the variant that keeps X_L in LDS for both coefficient sets

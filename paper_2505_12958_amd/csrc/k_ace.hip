@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     const int32_t* __restrict__ count, int cap, const double* __restrict__ lambda,
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     int32_t* __restrict__ counter, double* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace) {
+    double* __restrict__ vir, double* __restrict__ e_raw, int32_t* __restrict__ nbr_ace,
+    int vir_acc) {
   extern __shared__ double lds[];
   const int nnl = a.nnl, nlm = a.nlm, nA = a.nA, xs = a.max_xsize;
   double* A = lds;                               // [nA]
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(kAceThreads) void k_ace_fp64(
     }
     for (int k = 0; k < 9; ++k) {
       const double v = block_sum_f64<kAceThreads / 64>(w9[k], red + 8);
-      if (tid == 0 && vir) vir[(int64_t)k * n + i] = v;
+      if (tid == 0 && vir) vir[(int64_t)k * n + i] = vir_acc ? vir[(int64_t)k * n + i] + v : v;
     }
     if (tid == 0) {
       e_atom[i] += lam * E;
@@ -304,7 +305,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
                       const int32_t* ace_list, const int32_t* n_ace, int32_t* ace_row,
                       int32_t* counter, void* pair_g, double* e_atom, double* vir_atom,
                       double* e_raw, int32_t* nbr_ace, int32_t* halo, int32_t stamp,
-                      hipStream_t s) {
+                      bool vir_acc, hipStream_t s) {
   (void)ace_row;
   hipError_t e = hipSuccess;
   int dev = 0, n_cu = 256;
@@ -325,7 +326,7 @@ hipError_t launch_ace(const Ctx& c, const SysView& sv, const double* pos, const 
   }
   hipLaunchKernelGGL(k_ace_fp64, dim3(blocks), dim3(kAceThreads), lds, s, sv, c.ace, pos, pos4, nbr,
                      count, cap, lambda, ace_list, n_ace, n_atoms, counter, (double*)pair_g, e_atom,
-                     vir_atom, e_raw, nbr_ace);
+                     vir_atom, e_raw, nbr_ace, vir_acc ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
     const int32_t* __restrict__ ace_list, const int32_t* __restrict__ n_ace_p, int n_all,
     const float* __restrict__ A_in, const float* __restrict__ om_in,
     const float* __restrict__ phi_in, float* __restrict__ pair_g, double* __restrict__ e_atom,
-    double* __restrict__ vir, double* __restrict__ e_raw) {
+    double* __restrict__ vir, double* __restrict__ e_raw, int vir_acc) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -240,7 +240,10 @@ __global__ __launch_bounds__(64 * kBasisWaves) void k_ace_grad(
   for (int k = 0; k < 9; ++k) w9[k] = wave_sum_f64(w9[k]);
   if (lane == 0) {
     if (vir)
-      for (int k = 0; k < 9; ++k) vir[(int64_t)k * n + a] = w9[k];
+      for (int k = 0; k < 9; ++k) {
+        double* v = vir + (int64_t)k * n + a;
+        *v = vir_acc ? *v + w9[k] : w9[k];
+      }
     e_atom[a] += lam * E;
     if (e_raw) e_raw[a] = E;
   }
@@ -262,7 +265,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
                             float* pair_g, float* A_buf, float* om_buf, float* phi_buf,
                             float* bn_buf, double* e_atom, double* vir_atom, hipStream_t s,
                             int phase, int rank_mode, double* e_raw, int32_t* nbr_ace,
-                            int32_t* halo, int32_t stamp) {
+                            int32_t* halo, int32_t stamp, bool vir_acc) {
   const MixDev& m = c.mix;
   // grids are sized for every atom; wavefronts past *n_ace leave at once
   const int blocks = (n_atoms + kBasisWaves - 1) / kBasisWaves;
@@ -324,7 +327,7 @@ hipError_t launch_ace_mixed(const Ctx& c, const SysView& sv, const double* pos, 
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kBasisWaves), lds, s, sv, m, pos, pos4, nbr,
                          count, cap, lambda, ace_list, n_ace, n_atoms, A_buf, om_buf, phi_buf,
-                         pair_g, e_atom, vir_atom, e_raw);
+                         pair_g, e_atom, vir_atom, e_raw, vir_acc ? 1 : 0);
     };
     if (m.n_max == 8 && m.l_max == 4 && m.K == 8) go(k_ace_grad<8, 4, 8>);
     else if (m.n_max == 6 && m.l_max == 3 && m.K == 6) go(k_ace_grad<6, 3, 6>);
