@@ -1161,7 +1161,7 @@ ap_status ap_eam_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
                     force, vir, acc, (double*)ctx->e_eam_raw.p, s));
   }
   // in a fused evaluation the ACE call reduces the EAM and ACE per-atom virials together
-  if (virial && !ctx->fuse_virial && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
+  if (virial && !ctx->fused_eval && (st = reduce_into(ctx, sv, vir, 9, virial, acc, s))) return st;
   return AP_OK;
 }
 
@@ -1193,12 +1193,12 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   double* vir = virial ? (double*)ctx->vir_atom.p : nullptr;
   if (!acc) AP_HIP(launch_fill_f64(e_atom, 0.0, N, s));
   // a fused evaluation adds the ACE per-atom virial to the EAM call's
-  const bool vir_acc = vir && ctx->fuse_virial;
+  const bool vir_acc = vir && ctx->fused_eval;
   if (vir && !vir_acc) AP_HIP(launch_fill_f64(vir, 0.0, 9 * N, s));
   if ((st = ensure(ctx, ctx->pos4, 32 * (size_t)std::max<int64_t>(N, 1)))) return st;
-  AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
+  // a fused evaluation's EAM call packed these positions already
+  if (!ctx->fused_eval) AP_HIP(launch_pack_pos((int32_t)N, pos, (double4*)ctx->pos4.p, s));
   AP_HIP(launch_ace_rows((int32_t)N, ace_list, n_ace, (int32_t*)ctx->ace_row.p, s));
-  AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
   // the ACE kernels stamp the listed atoms and their neighbours (the atoms the
   // gather visits) in the halo array with a fresh stamp per evaluation; a new
   // allocation, or the stamp running out of range, clears it once.  A stale
@@ -1214,6 +1214,8 @@ ap_status ap_ace_forces(ap_ctx* c, const ap_systems* sys, const double* pos, con
   int32_t* halo = (int32_t*)ctx->ace_halo.p;
   if (ctx->precision == AP_PREC_FP64) {
     PhaseTimer timer(ctx, AP_PHASE_ACE, s);
+    // the FP64 kernel takes atoms from a work counter
+    AP_HIP(launch_ace_reset((int32_t*)ctx->ace_counter.p, s));
     AP_HIP(launch_ace(*ctx, sv, pos, (const double4*)ctx->pos4.p, nl->nbr, nl->count, nl->capacity,
                       (int32_t)N, lambda, ace_list, n_ace, (int32_t*)ctx->ace_row.p,
                       (int32_t*)ctx->ace_counter.p, ctx->pair_g.p, e_atom, vir,
@@ -1531,12 +1533,13 @@ static ap_status force_eval(Ctx* ctx, const ap_systems* sys, ap_md_state* st, hi
   }
   bool written = false;
   {
-    // EAM then ACE: one reduction of their summed per-atom virials
+    // EAM then ACE on the same positions: the positions are packed once and,
+    // with a virial, the summed per-atom virials are reduced once
     struct Unfuse {
       Ctx* c;
-      ~Unfuse() { c->fuse_virial = false; }
+      ~Unfuse() { c->fused_eval = false; }
     } unfuse{ctx};
-    ctx->fuse_virial = ctx->has_eam && ctx->has_ace && st->virial != nullptr;
+    ctx->fused_eval = ctx->has_eam && ctx->has_ace;
     if (ctx->has_eam) {
       if ((r = ap_eam_forces((ap_ctx*)ctx, sys, st->pos, &st->nl, st->lambda, st->e_atom, st->force,
                              st->virial, AP_OVERWRITE, s)))

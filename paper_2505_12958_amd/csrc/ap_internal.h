@@ -209,9 +209,11 @@ struct Ctx {
   std::string tune_cache;               // cache file path ("" = none)
   int last_rank_mode = -1;
   size_t ace_lds = 0;
-  // set by ap_step's force evaluation: the EAM call leaves its per-atom virial
-  // unreduced and the ACE call adds to it and reduces both at once
-  bool fuse_virial = false;
+  // set by ap_step's force evaluation, whose EAM and ACE calls see the same
+  // positions: the ACE call reuses the positions the EAM call packed, and with
+  // a virial the EAM call leaves its per-atom virial unreduced and the ACE call
+  // adds to it and reduces both at once
+  bool fused_eval = false;
   // algorithmic work counts (ap_info)
   double flops_atom = 0, flops_contract = 0, flops_bond = 0, nnz = 0, x_rows = 0;
   double mix_tiles = 0;        // stored 16x32 coefficient tiles (mixed path)
