@@ -61,3 +61,29 @@ def test_mixed_ace_component(name):
     # the ACE part alone meets the path's accuracy target on its own
     assert ef <= 1e-5
     assert ee <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [(ap.AP_PREC_FP64, 1e-10), (ap.AP_PREC_MIXED, 1e-5)])
+@pytest.mark.parametrize("name", ["wslab10", "batch6"])
+def test_md_force_evaluation(name, precision, tol):
+    """The force evaluation of ap_step (EAM, then ACE adding its per-atom
+    virial to the EAM call's before one reduction, on positions packed once)
+    against the oracle, with the indenter off: forces, system energies and
+    virials of a slab where both potentials contribute, and of a batch."""
+    import torch
+    wl, ref = case(name)
+    ctx = ap.Context(wl.eam, wl.ace, precision)
+    md = ap.MD(wl)
+    md.c.ind_K = 0.0
+    ctx.step(md.sys, md, 0)
+    torch.cuda.synchronize()
+    ctx.check()
+    F = md.force.cpu().numpy().T
+    W = md.virial.cpu().numpy().reshape(-1, 3, 3)
+    E = md.e_sys.cpu().numpy()
+    ctx.close()
+    ef = rel(F, ref["forces"])
+    ee = float(np.abs(E - ref["e_sys"]).max() / np.abs(ref["e_sys"]).max())
+    ew = rel(W, ref["virial"])
+    print(f"{name} precision {precision}: force {ef:.2e} energy {ee:.2e} virial {ew:.2e}")
+    assert ef <= tol and ee <= tol and ew <= tol
